@@ -1,0 +1,87 @@
+/*
+ * CPU oracle of the USP-ESBGK per-time-step particle method
+ * (Fei, Zhang, Li, Liu, "A Unified Stochastic Particle Bhatnagar-Gross-Krook
+ * Method for Multiscale Gas Flows", arXiv 1808.03801).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, serial, FP64 restatement of the
+ * method (Section 3.2, Table 2) used to check the GPU library.  It shares no
+ * code with the GPU path.  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load it; the product never does.
+ *
+ * Every floating-point computation is done in double precision; particle
+ * state is *stored* in the configured precision (float or double) so that the
+ * stored numbers are the ones a single-precision solver would hold.
+ */
+#ifndef USP_ORACLE_H
+#define USP_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Configuration: plain numbers, filled by the caller. */
+typedef struct {
+    /* gas: Eq. 35 viscosity law, Pr of Eq. 6 */
+    double m, kB, mu_ref, T_ref, omega, Pr;
+    /* uniform Cartesian grid; 1-D resolves y only, 2-D resolves x and y */
+    int dim, nx, ny;
+    double x0, x1, y0, y1, dx, dy, inv_dx, inv_dy, vcell;
+    /* faces 0..3 = x-lo, x-hi, y-lo, y-hi; kind 0 diffuse, 1 specular, 2 periodic */
+    int face_kind[4];
+    double face_T[4];
+    double face_u[12];
+    double accel[3];
+    /* numerics */
+    double dt, Np, r_p, Kn_c, pne_fixed;
+    int pne_mode, n_avg, avg_start, precision, weight_mode, conserve_mode, max_ppc;
+    /* moments that build the added particles and f_G: 0 instantaneous (Eq. 1),
+     * 1 time-averaged (Eq. 34); 1 = project each added batch onto zero mass,
+     * momentum and energy */
+    int jmom_mode, spawn_projection;
+    uint32_t seed_lo, seed_hi;
+} uspo_config;
+
+/* per-cell state record: centred moments, raw sums, averaged raw sums of f^n,
+ * averaged raw sums of f-tilde^*, P_ne^n, P_ne^{n-1} */
+#define USPO_MOM 13
+#define USPO_CS (4 * USPO_MOM + 2)
+/* derived field record (see uspo_get_fields) */
+#define USPO_NF 18
+/* per-cell diagnostics of the last step */
+#define USPO_NDIAG 32
+
+typedef struct uspo uspo;
+
+uspo* uspo_create(const uspo_config* cfg, const double* init_n, const double* init_u,
+                  const double* init_T);
+void uspo_destroy(uspo* o);
+int uspo_step(uspo* o, int nsteps);
+int uspo_error(const uspo* o);
+long long uspo_num_particles(const uspo* o);
+int uspo_ncell(const uspo* o);
+int uspo_get_state(const uspo* o, int* counts, double* parts, double* cellstate, int* step,
+                   int* n_samples);
+int uspo_set_state(uspo* o, const int* counts, const double* parts, const double* cellstate,
+                   int step, int n_samples);
+int uspo_get_fields(const uspo* o, int which, double* out);
+int uspo_get_diag(const uspo* o, double* out);
+
+/* pieces exposed for pinning */
+void uspo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double uspo_uniform(uint32_t r, int precision);
+void uspo_normal3(const uint32_t r[4], int precision, double z[3]);
+double uspo_time_sample(double u, double x, double nu_es, double dt);
+int uspo_test_spawn(const uspo_config* cfg, const double mom[USPO_MOM], int n_particles,
+                    double pne, int batch, int starred, int cell, int step, double* out,
+                    int max_out);
+int uspo_test_fields(const uspo_config* cfg, const double* parts, int n, double* out_mom,
+                     double* out_fields);
+int uspo_test_advect(const uspo_config* cfg, double* part6, int src_cell, int slot, int step);
+int uspo_test_pne(const uspo_config* cfg, const double* mom, double* pne_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

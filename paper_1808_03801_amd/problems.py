@@ -1,0 +1,312 @@
+"""Problem statements (inputs) for the USP-ESBGK particle solver.
+
+This module only *describes* problems: gas constants, geometry, boundary
+conditions, numerics and the initial macroscopic fields of every cell.  It
+holds none of the solver's per-step arithmetic; the GPU library and the CPU
+oracle each receive the plain numbers built here and compute everything else
+with their own code.
+
+Setup quantities that the paper's Section 4 uses to *choose* a workload
+(standard-state number density, the mean free path of Eq. 36 and the mean
+collision time of Eq. 37 at the initial state) are evaluated here once, so
+that a time step "dt = 5 tau_c" or a channel height "H = lambda_0 / Kn"
+becomes one double that both solvers receive bit-identically.
+
+Gas constants follow the paper's argon setup (Section 4, Eq. 35): the paper
+gives no numeric m, mu_ref, T_ref or Pr; the values used are argon's
+(m = 6.63e-26 kg, mu_ref = 2.117e-5 Pa s at 273 K, Pr = 2/3).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field
+from typing import List, Sequence
+
+import numpy as np
+
+K_B = 1.380649e-23
+M_AR = 6.63e-26
+MU_REF_AR = 2.117e-5
+T_REF_AR = 273.0
+P_ATM = 101325.0
+
+# boundary kinds (same integer codes on both solvers' interfaces)
+BC_DIFFUSE, BC_SPECULAR, BC_PERIODIC = 0, 1, 2
+# P_ne modes: fixed value, GLL Knudsen number from instantaneous or
+# time-averaged fields (Eq. 16-18)
+PNE_FIXED, PNE_GLL_INST, PNE_GLL_AVG = 0, 1, 2
+# weight of added particles: consistent with the represented PDF for every
+# dt*nu_ES, or Eq. 26 as printed
+WEIGHT_CONSISTENT, WEIGHT_LITERAL = 0, 1
+# per-cell conservation after the relaxation step
+CONSERVE_FULL, CONSERVE_NONE = 0, 1
+# moments that build the added particles and the ES target: instantaneous
+# (Eq. 1) or exponentially time-averaged (Eq. 34, steady flows)
+JMOM_INST, JMOM_AVG = 0, 1
+
+FACE_XLO, FACE_XHI, FACE_YLO, FACE_YHI = 0, 1, 2, 3
+
+
+@dataclass
+class Gas:
+    m: float = M_AR
+    kB: float = K_B
+    mu_ref: float = MU_REF_AR
+    T_ref: float = T_REF_AR
+    omega: float = 0.81
+    Pr: float = 2.0 / 3.0
+
+    @property
+    def R(self) -> float:
+        return self.kB / self.m
+
+    def mu(self, T: float) -> float:
+        return self.mu_ref * (T / self.T_ref) ** self.omega
+
+    def mean_free_path(self, rho: float, p: float, T: float) -> float:
+        # Eq. 36
+        return 16.0 / (5.0 * math.sqrt(2.0 * math.pi)) * self.mu(T) / math.sqrt(rho * p)
+
+    def mean_speed(self, T: float) -> float:
+        return math.sqrt(8.0 * self.kB * T / (math.pi * self.m))
+
+    def collision_time(self, rho: float, p: float, T: float) -> float:
+        # Eq. 37
+        return self.mean_free_path(rho, p, T) / self.mean_speed(T)
+
+
+@dataclass
+class Face:
+    kind: int = BC_SPECULAR
+    T: float = 273.0
+    u: Sequence[float] = (0.0, 0.0, 0.0)
+
+
+@dataclass
+class Problem:
+    """A complete, plain-number description of one solver instance.
+
+    1-D problems resolve the y axis only (cells along y, the x extent is one
+    unit-length slab); 2-D problems resolve x and y.  Velocities always carry
+    three components.  Cells are numbered iy * nx + ix.
+    """
+
+    name: str
+    gas: Gas
+    dim: int
+    nx: int
+    ny: int
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    dx: float
+    dy: float
+    inv_dx: float
+    inv_dy: float
+    vcell: float
+    faces: List[Face]
+    accel: Sequence[float]
+    dt: float
+    Np: float
+    init_n: np.ndarray  # [ncell] number density (1/m^3)
+    init_u: np.ndarray  # [ncell, 3] m/s
+    init_T: np.ndarray  # [ncell] K
+    r_p: float = 10.0
+    Kn_c: float = 0.1
+    pne_mode: int = PNE_GLL_AVG
+    pne_fixed: float = 1.0
+    n_avg: int = 1000
+    avg_start: int = 0
+    precision: int = 32
+    weight_mode: int = WEIGHT_CONSISTENT
+    conserve_mode: int = CONSERVE_FULL
+    seed: int = 0
+    max_ppc: int = 2048
+    jmom_mode: int = JMOM_INST
+    spawn_projection: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ncell(self) -> int:
+        return self.nx * self.ny
+
+    def replace(self, **kw) -> "Problem":
+        return dataclasses.replace(self, **kw)
+
+    def expected_particles(self) -> int:
+        return int(np.sum(np.floor(self.init_n * self.vcell / self.Np + 0.5)))
+
+
+def _faces_1d(lo: Face, hi: Face) -> List[Face]:
+    # x faces are inert in 1-D
+    return [Face(BC_PERIODIC), Face(BC_PERIODIC), lo, hi]
+
+
+def _grid_1d(ny: int, H: float):
+    dy = H / ny
+    return dict(dim=1, nx=1, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=H, dx=1.0, dy=dy,
+                inv_dx=1.0, inv_dy=ny / H, vcell=dy)
+
+
+def standard_state(gas: Gas, T0: float = 273.0, p0: float = P_ATM):
+    n0 = p0 / (gas.kB * T0)
+    rho0 = gas.m * n0
+    lam0 = gas.mean_free_path(rho0, p0, T0)
+    tau0 = gas.collision_time(rho0, p0, T0)
+    return n0, rho0, lam0, tau0
+
+
+def couette_1d(Kn=0.1, U_w=100.0, T_w=273.0, ncell=100, ppc=100, dt_over_tau=1.0,
+               omega=0.5, precision=64, seed=0, pne_mode=PNE_GLL_AVG, name="couette") -> Problem:
+    """Planar Couette flow between diffuse plates moving at -U_w (bottom) and
+    +U_w (top) along x (Section 4.1); Kn = lambda_0 / H."""
+    gas = Gas(omega=omega)
+    n0, rho0, lam0, tau0 = standard_state(gas, T_w)
+    H = lam0 / Kn
+    g = _grid_1d(ncell, H)
+    return Problem(name=name, gas=gas, **g,
+                   faces=_faces_1d(Face(BC_DIFFUSE, T_w, (-U_w, 0.0, 0.0)),
+                                   Face(BC_DIFFUSE, T_w, (U_w, 0.0, 0.0))),
+                   accel=(0.0, 0.0, 0.0), dt=dt_over_tau * tau0, Np=n0 * g["vcell"] / ppc,
+                   init_n=np.full(ncell, n0), init_u=np.zeros((ncell, 3)),
+                   init_T=np.full(ncell, T_w), precision=precision, seed=seed,
+                   pne_mode=pne_mode,
+                   meta=dict(H=H, lam0=lam0, tau0=tau0, n0=n0, U_w=U_w, T_w=T_w, Kn=Kn))
+
+
+def thermal_couette_1d(Kn=1e-3, dT=10.0, T_w=273.0, ncell=1000, ppc=500, dt_over_tau=5.0,
+                       omega=0.81, precision=32, seed=0, init_ns=True,
+                       pne_mode=PNE_GLL_AVG, jmom_mode=JMOM_AVG, spawn_projection=1,
+                       name="thermal_couette") -> Problem:
+    """Stationary diffuse plates at T_w + dT (bottom) and T_w - dT (top)
+    (Section 4.1).  With init_ns the gas starts on the Fourier profile of a
+    gas with mu ~ T^omega (T^(1+omega) linear in y) at uniform pressure."""
+    gas = Gas(omega=omega)
+    n0, rho0, lam0, tau0 = standard_state(gas, T_w)
+    H = lam0 / Kn
+    g = _grid_1d(ncell, H)
+    yc = (np.arange(ncell) + 0.5) * g["dy"]
+    Tb, Tt = T_w + dT, T_w - dT
+    if init_ns:
+        a = omega + 1.0
+        T = (Tb ** a + (Tt ** a - Tb ** a) * yc / H) ** (1.0 / a)
+    else:
+        T = np.full(ncell, T_w)
+    n = P_ATM / (gas.kB * T)
+    return Problem(name=name, gas=gas, **g,
+                   faces=_faces_1d(Face(BC_DIFFUSE, Tb), Face(BC_DIFFUSE, Tt)),
+                   accel=(0.0, 0.0, 0.0), dt=dt_over_tau * tau0, Np=n0 * g["vcell"] / ppc,
+                   init_n=n, init_u=np.zeros((ncell, 3)), init_T=T, precision=precision,
+                   seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
+                   spawn_projection=spawn_projection,
+                   meta=dict(H=H, lam0=lam0, tau0=tau0, n0=n0, T_bottom=Tb, T_top=Tt, Kn=Kn))
+
+
+def sod_1d(Kn=1e-3, L=1.0, ncell=1000, mean_ppc=500, rho_ratio=8.0, p_ratio=10.0,
+           T_l=273.0, dt_over_tau=5.0, omega=0.81, precision=32, seed=0,
+           pne_mode=PNE_GLL_INST, jmom_mode=JMOM_AVG, spawn_projection=1,
+           name="sod") -> Problem:
+    """Sod shock tube along the resolved axis (Section 4.3), closed by
+    specular ends.  rho_l is chosen so that lambda_l = Kn * L.  At a few
+    hundred particles per cell and dt = 5 tau_c the instantaneous-moment
+    scheme is unstable (the paper used 2.5e4-2e5 particles per cell), so the
+    stress and heat flux of the added particles are time-averaged here too."""
+    gas = Gas(omega=omega)
+    T_r = T_l * rho_ratio / p_ratio
+    lam_l = Kn * L
+    c = 16.0 / (5.0 * math.sqrt(2.0 * math.pi))
+    rho_l = c * gas.mu(T_l) / (lam_l * math.sqrt(gas.R * T_l))
+    n_l = rho_l / gas.m
+    n_r = n_l / rho_ratio
+    p_l = n_l * gas.kB * T_l
+    tau_l = gas.collision_time(rho_l, p_l, T_l)
+    g = _grid_1d(ncell, L)
+    yc = (np.arange(ncell) + 0.5) * g["dy"]
+    left = yc < 0.5 * L
+    n = np.where(left, n_l, n_r)
+    T = np.where(left, T_l, T_r)
+    ppc_l = 2.0 * mean_ppc * rho_ratio / (rho_ratio + 1.0)
+    return Problem(name=name, gas=gas, **g,
+                   faces=_faces_1d(Face(BC_SPECULAR), Face(BC_SPECULAR)),
+                   accel=(0.0, 0.0, 0.0), dt=dt_over_tau * tau_l, Np=n_l * g["vcell"] / ppc_l,
+                   init_n=n, init_u=np.zeros((ncell, 3)), init_T=T, precision=precision,
+                   seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
+                   spawn_projection=spawn_projection,
+                   meta=dict(L=L, lam_l=lam_l, tau_l=tau_l, rho_l=rho_l, p_l=p_l, T_r=T_r, Kn=Kn))
+
+
+def poiseuille_1d(Kn=1e-3, dpdx=4.0e6, T_w=273.0, ncell=100, ppc=500, dt_over_tau=5.0,
+                  omega=0.81, precision=32, seed=0, pne_mode=PNE_GLL_AVG,
+                  jmom_mode=JMOM_AVG, spawn_projection=1, name="poiseuille") -> Problem:
+    """Plane Poiseuille flow (Section 4.2, Table 3) driven by a uniform body
+    acceleration a_x = (dp/dx) / rho_0 along the plates."""
+    gas = Gas(omega=omega)
+    n0, rho0, lam0, tau0 = standard_state(gas, T_w)
+    H = lam0 / Kn
+    g = _grid_1d(ncell, H)
+    return Problem(name=name, gas=gas, **g,
+                   faces=_faces_1d(Face(BC_DIFFUSE, T_w), Face(BC_DIFFUSE, T_w)),
+                   accel=(dpdx / rho0, 0.0, 0.0), dt=dt_over_tau * tau0,
+                   Np=n0 * g["vcell"] / ppc, init_n=np.full(ncell, n0),
+                   init_u=np.zeros((ncell, 3)), init_T=np.full(ncell, T_w),
+                   precision=precision, seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
+                   spawn_projection=spawn_projection,
+                   meta=dict(H=H, lam0=lam0, tau0=tau0, rho0=rho0, n0=n0, dpdx=dpdx, T_w=T_w,
+                             Kn=Kn))
+
+
+def cavity_2d(Kn=1e-3, n=128, ppc=200, U_lid=50.0, T_w=273.0, omega=0.81, precision=32,
+              seed=0, pne_mode=PNE_GLL_AVG, jmom_mode=JMOM_AVG, spawn_projection=1,
+              name="cavity") -> Problem:
+    """Lid-driven square cavity (Section 4.4): four diffuse walls at T_w, the
+    top one moving at U_lid along x; dt = 0.3 dx / mean speed (the
+    dt/tau_c = 0.3 dx/lambda entry of Tables 5-6)."""
+    gas = Gas(omega=omega)
+    n0, rho0, lam0, tau0 = standard_state(gas, T_w)
+    L = lam0 / Kn
+    d = L / n
+    still = Face(BC_DIFFUSE, T_w)
+    faces = [still, still, still, Face(BC_DIFFUSE, T_w, (U_lid, 0.0, 0.0))]
+    nc = n * n
+    return Problem(name=name, gas=gas, dim=2, nx=n, ny=n, x0=0.0, x1=L, y0=0.0, y1=L, dx=d,
+                   dy=d, inv_dx=n / L, inv_dy=n / L, vcell=d * d, faces=faces,
+                   accel=(0.0, 0.0, 0.0), dt=0.3 * d / gas.mean_speed(T_w),
+                   Np=n0 * d * d / ppc, init_n=np.full(nc, n0), init_u=np.zeros((nc, 3)),
+                   init_T=np.full(nc, T_w), precision=precision, seed=seed, pne_mode=pne_mode,
+                   jmom_mode=jmom_mode, spawn_projection=spawn_projection,
+                   meta=dict(L=L, lam0=lam0, tau0=tau0, n0=n0, U_lid=U_lid, Kn=Kn))
+
+
+def homogeneous_box(ncell=64, ppc=1000, nu_dt=1.0, T=273.0, precision=64, seed=0,
+                    pne=1.0, omega=0.5, name="box") -> Problem:
+    """Spatially homogeneous gas in a periodic 1-D box whose cells are
+    independent replicas; dt is set so that nu * dt = nu_dt at (n0, T)."""
+    gas = Gas(omega=omega)
+    n0, rho0, lam0, tau0 = standard_state(gas, T)
+    nu = P_ATM / gas.mu(T)
+    H = 100.0 * lam0
+    g = _grid_1d(ncell, H)
+    per = Face(BC_PERIODIC)
+    return Problem(name=name, gas=gas, **g, faces=_faces_1d(per, per),
+                   accel=(0.0, 0.0, 0.0), dt=nu_dt / nu, Np=n0 * g["vcell"] / ppc,
+                   init_n=np.full(ncell, n0), init_u=np.zeros((ncell, 3)),
+                   init_T=np.full(ncell, T), precision=precision, seed=seed,
+                   pne_mode=PNE_FIXED, pne_fixed=pne,
+                   meta=dict(n0=n0, nu=nu, tau0=tau0, lam0=lam0, H=H))
+
+
+def config(name: str, **kw) -> Problem:
+    """The named workloads: C1 Couette (FP64), C2 thermal Couette and Sod,
+    C3 cavity at three Kn."""
+    if name == "c1":
+        return couette_1d(**kw)
+    if name == "c2_tc":
+        return thermal_couette_1d(**kw)
+    if name == "c2_sod":
+        return sod_1d(**kw)
+    if name.startswith("c3"):
+        kn = {"c3": 1e-3, "c3_kn1e-3": 1e-3, "c3_kn1e-2": 1e-2, "c3_kn1e-1": 0.1}[name]
+        return cavity_2d(Kn=kn, **kw)
+    raise KeyError(name)
