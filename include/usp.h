@@ -1,0 +1,181 @@
+/*
+ * libusp: MI355X (gfx950) particle solver for the unified stochastic particle
+ * ES-BGK method (USP-ESBGK) of Fei, Zhang, Li and Liu, "A Unified Stochastic
+ * Particle Bhatnagar-Gross-Krook Method for Multiscale Gas Flows"
+ * (arXiv 1808.03801).
+ *
+ * One call of usp_step advances every listed instance by the per-time-step
+ * algorithm of Table 2 (steps 2-8): added particles for f-hat^n (Eq. 22,
+ * 25-26), advection with wall reflection, a stable counting sort by cell,
+ * the moments of f-tilde^* and the starred stress / heat flux (Eq. 33),
+ * added particles for f^* (Eq. 24), Bernoulli selection and reassignment
+ * (Eq. 9, 28), resampling from the time-dependent ES Gaussian (Eq. 6, 29-32),
+ * added particles for the last term of Eq. 27, a per-cell conservation
+ * correction, the moments of f^{n+1} (Eq. 1), their time average (Eq. 34) and
+ * P_ne (Eq. 16-18).  All of it runs in HIP kernels on the device.
+ *
+ * Conventions
+ *  - Every function returns a usp_status; 0 is success.  The text of the last
+ *    error of a context is returned by usp_last_error.
+ *  - Argument errors are reported synchronously.  Errors raised inside the
+ *    kernels (capacity, window) are sticky per instance and reported by the
+ *    next usp_sync / usp_get_* call on it; a failed instance refuses further
+ *    steps with USP_ESTATE, other instances continue.
+ *  - The context owns all device memory it allocates (through the caller's
+ *    allocator if one is given).  The caller owns every host buffer passed in.
+ *  - All work is enqueued on the context's HIP stream; usp_step returns
+ *    without waiting.
+ *  - 1-D problems resolve y only; 2-D problems resolve x and y; velocities
+ *    always have three components; cells are numbered iy * nx + ix.
+ *  - Host particle records are [x, y, cx, cy, cz, w] doubles in canonical
+ *    order (cell by cell; within a cell the order the algorithm defines).
+ */
+#ifndef USP_H
+#define USP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    USP_OK = 0,
+    USP_EINVAL = -1,    /* bad argument or configuration */
+    USP_ENOMEM = -2,    /* device allocation failed / footprint above budget */
+    USP_ECAPACITY = -3, /* a cell exceeded max_ppc particles (instance poisoned) */
+    USP_EWINDOW = -4,   /* a particle moved farther than the sort window (poisoned) */
+    USP_EDEVICE = -5,   /* a HIP runtime call failed */
+    USP_ESTATE = -7,    /* instance unknown, freed or poisoned */
+    USP_ENOLIB = -8     /* built without device support */
+} usp_status;
+
+enum { USP_BC_DIFFUSE = 0, USP_BC_SPECULAR = 1, USP_BC_PERIODIC = 2 };
+enum { USP_PNE_FIXED = 0, USP_PNE_GLL_INST = 1, USP_PNE_GLL_AVG = 2 };
+enum { USP_WEIGHT_CONSISTENT = 0, USP_WEIGHT_LITERAL = 1 };
+enum { USP_CONSERVE_FULL = 0, USP_CONSERVE_NONE = 1 };
+enum { USP_JMOM_INST = 0, USP_JMOM_AVG = 1 };
+
+/* Gas (Section 4): Eq. 35 viscosity mu = mu_ref (T / T_ref)^omega; Pr of
+ * Eq. 6 (nu_ES = Pr nu); molecular mass m and Boltzmann constant kB. */
+typedef struct {
+    double m, kB, mu_ref, T_ref, omega, Pr;
+} usp_gas;
+
+/* A face of the domain: kind USP_BC_*, wall temperature T and wall velocity u
+ * (diffuse faces; full accommodation). */
+typedef struct {
+    int kind;
+    double T;
+    double u[3];
+} usp_face;
+
+/* Geometry.  Domain [x0, x1] x [y0, y1] with nx * ny uniform cells of widths
+ * dx, dy (inv_dx = 1/dx, inv_dy = 1/dy supplied so that every solver uses the
+ * same numbers); vcell = cell volume (per unit depth / area in 2-D / 1-D).
+ * face[0..3] = x-lo, x-hi, y-lo, y-hi (x faces are unused in 1-D).
+ * accel = uniform body acceleration (the Poiseuille drive), m/s^2. */
+typedef struct {
+    int dim, nx, ny;
+    double x0, x1, y0, y1, dx, dy, inv_dx, inv_dy, vcell;
+    usp_face face[4];
+    double accel[3];
+} usp_problem;
+
+/* Numerics.  dt: time step (s); Np: real molecules per unit weight; r_p:
+ * Eq. 25 scale (10 in the paper); Kn_c: Eq. 16 reference Knudsen number
+ * (0.1); pne_mode: USP_PNE_*, pne_fixed used by USP_PNE_FIXED; n_avg: Eq. 34
+ * window (1000) and avg_start: first averaged step; precision: 32 or 64
+ * (particle state); max_ppc: largest number of particles a cell may hold
+ * during a step (<= 2048); jmom_mode: moments that build the added particles
+ * and the ES target (instantaneous Eq. 1 or averaged Eq. 34);
+ * spawn_projection: 1 = project each added batch onto zero mass, momentum and
+ * energy; window: sort-window half width in cells (0 = derive from the
+ * initial state). */
+typedef struct {
+    double dt, Np, r_p, Kn_c, pne_fixed;
+    int pne_mode, n_avg, avg_start, precision, weight_mode, conserve_mode, max_ppc;
+    int jmom_mode, spawn_projection, window;
+    uint64_t seed;
+} usp_numerics;
+
+/* Device binding.  alloc/free: device allocator (NULL = hipMalloc/hipFree);
+ * user: passed back to them; stream: hipStream_t (NULL = null stream);
+ * device: HIP device ordinal; budget: bytes the context may allocate
+ * (0 = unlimited). */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+    void* stream;
+    int device;
+    size_t budget;
+} usp_device;
+
+typedef struct usp_ctx usp_ctx;
+
+/* Creates a context bound to one device and stream. */
+usp_status usp_create(const usp_device* dev, usp_ctx** out);
+/* Frees every instance and the context. */
+void usp_destroy(usp_ctx* ctx);
+/* Text of the last error of ctx (never NULL). */
+const char* usp_last_error(usp_ctx* ctx);
+
+/* Device bytes an instance of this problem needs (admission control). */
+usp_status usp_footprint(const usp_problem* pb, const usp_numerics* nm, size_t* bytes_out);
+
+/* Creates an instance and its initial state (Table 2 step 1): per cell
+ * round(n V / Np) particles, uniform positions, Maxwellian velocities at the
+ * cell's (u, T), weight 1; then the moments of f^0 and P_ne^0.  init_n [ncell]
+ * (1/m^3), init_u [ncell][3] (m/s), init_T [ncell] (K) are host arrays. */
+usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb,
+                             const usp_numerics* nm, const double* init_n,
+                             const double* init_u, const double* init_T, int* id_out);
+usp_status usp_instance_free(usp_ctx* ctx, int id);
+
+/* Advances the n_ids listed instances by nsteps time steps each, all of them
+ * in the same kernel launches (batched).  Asynchronous on the stream. */
+usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps);
+
+/* Waits for the stream; reports the first sticky instance error, if any. */
+usp_status usp_sync(usp_ctx* ctx);
+/* Sticky device error status of one instance (synchronises). */
+usp_status usp_instance_status(usp_ctx* ctx, int id);
+
+/* Number of cells / particles (synchronises). */
+usp_status usp_num_cells(usp_ctx* ctx, int id, int* ncell);
+usp_status usp_num_particles(usp_ctx* ctx, int id, long long* n);
+
+/* State transfer (synchronises).  counts [ncell]; parts [N][6]; cells
+ * [ncell][54] = centred moments (S0, u[3], K[6], Q[3]), raw sums (S0, S1[3],
+ * S2[6], S3[3]), time-averaged raw sums of f^n, of f-tilde^*, P_ne^n,
+ * P_ne^{n-1}.  get: parts may be NULL (counts only).  set: cells may be NULL
+ * (moments recomputed, averages cleared, P_ne from the fields). */
+usp_status usp_get_state(usp_ctx* ctx, int id, int* counts, double* parts, double* cells,
+                         int* step, int* n_samples);
+usp_status usp_set_state(usp_ctx* ctx, int id, const int* counts, const double* parts,
+                         const double* cells, int step, int n_samples);
+
+/* Field record per cell (which = 0 instantaneous, 1 time-averaged), [ncell][18]:
+ * S0, rho, u[3], T, p, sigma[6] (xx yy zz xy xz yz), q[3], P_ne, count. */
+usp_status usp_get_fields(usp_ctx* ctx, int id, int which, double* out);
+
+/* Per-cell diagnostics of the last step, [ncell][32] (enable first with
+ * usp_set_diag; costs one record write per cell per step). */
+usp_status usp_set_diag(usp_ctx* ctx, int id, int on);
+usp_status usp_get_diag(usp_ctx* ctx, int id, double* out);
+
+/* Launch shape: threads per cell workgroup (64..256, multiple of 64; 0 =
+ * default 256).  Applies to later usp_step calls. */
+usp_status usp_set_block(usp_ctx* ctx, int threads);
+
+/* Philox4x32-10 evaluated on the device for n counters (ctr [n][4], out
+ * [n][4], host arrays) with key (k0, k1); for checking the generator. */
+usp_status usp_philox(usp_ctx* ctx, const uint32_t* ctr, uint32_t k0, uint32_t k1, int n,
+                      uint32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,108 @@
+// Shared declarations of the libusp host runtime and its gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace usp {
+
+constexpr int NMOM = 13;   // centred moments / raw sums per cell
+constexpr int NDIAG = 32;  // per-cell diagnostic record
+constexpr int MAX_BINS = 256;
+constexpr int MAX_PPC = 2048;
+
+// control words of an instance (device memory)
+enum { CTL_CUR = 0, CTL_STEP = 1, CTL_NSAMP = 2, CTL_ERR = 3, CTL_N = 4 };
+// sticky error bits
+enum { ERR_CAPACITY = 1, ERR_WINDOW = 2 };
+
+// kernel modes
+enum {
+    MODE_RELAX = 1,    // Table 2 steps 4-8 on the gathered cell
+    MODE_MOVE = 2,     // step 2 + step 3 of the next step, write by destination bins
+    MODE_MOMENTS = 4   // only the moments of the gathered cell (initial state)
+};
+
+// Philox purposes (counter word 1 = purpose << 24 | sub)
+enum {
+    PUR_INIT_POS = 1,
+    PUR_INIT_VEL = 2,
+    PUR_SPAWN_CNT = 3,
+    PUR_SPAWN_POS = 4,
+    PUR_SPAWN_VEL = 5,
+    PUR_WALL = 6,
+    PUR_SELECT = 7,
+    PUR_RESAMPLE = 8
+};
+
+// diagnostic slots (same meaning as the host-side record)
+enum {
+    D_NIN = 0, D_N4, D_NSEL, D_NUSP, D_NDEL, D_N7, D_NOUT, D_N2, D_SSEL, D_PSEL, D_FLAGS,
+    D_CHOLFB, D_M0, D_P0X, D_P0Y, D_P0Z, D_E0, D_M1, D_P1X, D_P1Y, D_P1Z, D_E1, D_CLAMP,
+    D_MARG_SEL, D_MARG_ROUND, D_MARG_CNT, D_WR, D_S2, D_MARG_CNT2
+};
+enum { F_SKIP = 1, F_FAILMASS = 2, F_FAILENERGY = 4, F_NOUSP = 8 };
+
+// Everything a kernel needs to know about one solver instance.  Lives in
+// device memory; read-only during a launch.
+struct InstDev {
+    // gas
+    double m, kB, mu_ref, T_ref, omega, Pr, R, F;
+    // geometry
+    int dim, nx, ny, ncell;
+    double x0, x1, y0, y1, dx, dy, inv_dx, inv_dy, vcell, Np;
+    int face_kind[4];
+    double face_T[4];
+    double face_u[12];
+    double accel[3];
+    // numerics
+    double dt, r_p, Kn_c, pne_fixed;
+    int pne_mode, n_avg, avg_start, prec, weight_mode, conserve_mode, max_ppc, jmom_mode, proj;
+    uint32_t key0, key1;
+    // sort window: source offsets -Kx..Kx, -Ky..Ky; nb = (2Ky+1)(2Kx+1) bins
+    int Kx, Ky, nbx, nb;
+    int cap;  // particle slots per cell region (>= max_ppc)
+    // device arrays
+    void* pc[2][6];     // [buffer][x, y, cx, cy, cz, w]
+    uint32_t* tab[2];   // [buffer][cell][nb + 1] exclusive bin offsets
+    double* mom;        // [NMOM][ncell] centred moments of f^n
+    double* raw;        // [NMOM][ncell] raw sums of f^n
+    double* avg;        // [NMOM][ncell] Eq. 34 average of raw sums of f^n
+    double* avgs;       // [NMOM][ncell] Eq. 34 average of raw sums of f-tilde^*
+    double* pcur;       // [ncell] P_ne^n
+    double* pprev;      // [ncell] P_ne^{n-1}
+    int* cnt;           // [ncell] particles of f^n per cell
+    int* ctl;           // [CTL_N]
+    double* diag;       // [ncell][NDIAG] or null
+};
+
+struct Batch {
+    const InstDev* inst;  // [ninst]
+    const int* base;      // [ninst + 1] first global cell of each instance
+    int ninst;
+    int ncells;           // total cells
+    int mode;
+    int cap_lds;          // particle slots of the LDS list
+};
+
+// LDS bytes of the cell kernel for a given list capacity / state precision
+inline size_t lds_bytes(int cap, int real_bytes, int dim, int nb, int nthreads)
+{
+    size_t b = 0;
+    b += (size_t)(dim + 4) * cap * real_bytes;   // positions, velocities, weight
+    b += (size_t)cap * 4;                       // keys / inverse map
+    b += (size_t)cap * 4;                       // time-sample words
+    b += (size_t)cap * 2 * 2;                   // slots, bins
+    b += (size_t)cap;                           // fates
+    b = (b + 15) & ~(size_t)15;
+    b += (size_t)(nthreads / 64) * 24 * 8;      // reductions
+    b += 256 * 4;                               // histogram
+    b += (size_t)((cap + 63) / 64) * nb * 2;    // tile counts
+    b = (b + 15) & ~(size_t)15;
+    b += (size_t)(nb + 1) * 4 * 3;              // runs / bin offsets
+    b = (b + 15) & ~(size_t)15;
+    b += 64 * 8;                                // scalars
+    return b;
+}
+
+}  // namespace usp

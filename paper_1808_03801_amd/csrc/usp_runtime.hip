@@ -1,0 +1,768 @@
+// libusp host runtime: the C-ABI of include/usp.h over the gfx950 kernels.
+//
+// An instance owns two particle buffers (ping-pong) of ncell regions with
+// `cap` slots each, per-component arrays (SoA), a bin table per buffer, the
+// per-cell moment arrays and four control words (current buffer, step,
+// sample count, sticky error).  usp_step enqueues, per step, the fused cell
+// kernel, the P_ne kernel and the control kernel for all listed instances at
+// once; the first launch of a call only adds/advects (step 2-3) and the last
+// only relaxes, so that between calls the state is "every particle in its own
+// cell, in canonical order".
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/usp.h"
+#include "usp_common.h"
+
+namespace usp {
+template <typename real, int DIM>
+__global__ void cell_kernel(Batch B);
+template <typename real, int DIM>
+__global__ void init_kernel(Batch B, const double* init_n, const double* init_u,
+                            const double* init_T);
+__global__ void fields_kernel(Batch B, int init);
+__global__ void ctl_kernel(Batch B, int relaxed);
+__global__ void philox_kernel(const uint32_t* ctr, uint32_t k0, uint32_t k1, int n,
+                              uint32_t* out);
+__global__ void fields_out_kernel(Batch B, int which, double* out);
+}  // namespace usp
+
+using namespace usp;
+
+namespace {
+
+struct Instance {
+    InstDev h;            // host copy of the descriptor
+    InstDev* d = nullptr; // device copy (single-instance launches)
+    int* dbase = nullptr; // {0, ncell}
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+    bool alive = false;
+    bool diag_on = false;
+};
+
+}  // namespace
+
+struct usp_ctx {
+    usp_device dev;
+    hipStream_t stream = nullptr;
+    std::vector<Instance*> inst;
+    std::string err;
+    int block = 256;
+    size_t allocated = 0;
+    // batch descriptor cache
+    std::vector<int> last_ids;
+    InstDev* bd = nullptr;
+    int* bbase = nullptr;
+    int bcap = 0;
+};
+
+namespace {
+
+usp_status fail(usp_ctx* ctx, usp_status s, const std::string& msg)
+{
+    if (ctx) ctx->err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                               \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(ctx, USP_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+void* dalloc(usp_ctx* ctx, size_t bytes)
+{
+    void* p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (ctx->dev.budget && ctx->allocated + bytes > ctx->dev.budget) return nullptr;
+    if (ctx->dev.alloc) {
+        p = ctx->dev.alloc(bytes, ctx->dev.user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) ctx->allocated += bytes;
+    return p;
+}
+
+void dfree(usp_ctx* ctx, void* p, size_t bytes)
+{
+    if (!p) return;
+    if (ctx->dev.free) ctx->dev.free(p, ctx->dev.user);
+    else (void)hipFree(p);
+    ctx->allocated -= std::min(ctx->allocated, bytes);
+}
+
+struct Window {
+    int Kx, Ky;
+};
+
+int axis_limit(int n, bool periodic, int hard)
+{
+    int lim = periodic ? n / 2 : n - 1;
+    if (lim < 0) lim = 0;
+    return std::min(lim, hard);
+}
+
+// Half width of the sort window: the largest displacement in cells that a
+// particle of the initial state or a wall emission can make in one step,
+// from a six-sigma thermal speed plus the largest drift, with 30 % margin.
+Window choose_window(const usp_gas* gas, const usp_problem* pb, const usp_numerics* nm,
+                     const double* init_u, const double* init_T)
+{
+    const int ncell = pb->nx * pb->ny;
+    double vmax = 0.0;
+    for (int c = 0; c < ncell; ++c) {
+        const double* u = init_u + 3 * c;
+        const double s = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) +
+                         6.0 * sqrt(gas->kB * init_T[c] / gas->m);
+        vmax = std::max(vmax, s);
+    }
+    for (int f = 0; f < 4; ++f) {
+        const double* u = pb->face[f].u;
+        const double s = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) +
+                         6.0 * sqrt(gas->kB * pb->face[f].T / gas->m);
+        vmax = std::max(vmax, s);
+    }
+    vmax *= 1.3;
+    Window w;
+    const bool px = pb->face[0].kind == USP_BC_PERIODIC, py = pb->face[2].kind == USP_BC_PERIODIC;
+    if (pb->dim == 1) {
+        int k = nm->window > 0 ? nm->window : (int)ceil(vmax * nm->dt * pb->inv_dy) + 1;
+        w.Ky = std::min(k, axis_limit(pb->ny, py, 127));
+        w.Kx = 0;
+    } else {
+        int kx = nm->window > 0 ? nm->window : (int)ceil(vmax * nm->dt * pb->inv_dx) + 1;
+        int ky = nm->window > 0 ? nm->window : (int)ceil(vmax * nm->dt * pb->inv_dy) + 1;
+        w.Kx = std::min(kx, axis_limit(pb->nx, px, 7));
+        w.Ky = std::min(ky, axis_limit(pb->ny, py, 7));
+    }
+    return w;
+}
+
+usp_status validate(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb, const usp_numerics* nm)
+{
+    if (!gas || !pb || !nm) return fail(ctx, USP_EINVAL, "null argument");
+    if (pb->dim != 1 && pb->dim != 2) return fail(ctx, USP_EINVAL, "dim must be 1 or 2");
+    if (pb->nx < 1 || pb->ny < 1 || (pb->dim == 1 && pb->nx != 1))
+        return fail(ctx, USP_EINVAL, "bad grid");
+    if (!(nm->dt > 0) || !(nm->Np > 0) || !(pb->vcell > 0) || !(nm->r_p > 0))
+        return fail(ctx, USP_EINVAL, "dt, Np, vcell and r_p must be positive");
+    if (nm->precision != 32 && nm->precision != 64)
+        return fail(ctx, USP_EINVAL, "precision must be 32 or 64");
+    if (nm->max_ppc < 2 || nm->max_ppc > MAX_PPC)
+        return fail(ctx, USP_EINVAL, "max_ppc must be in [2, 2048]");
+    if (nm->n_avg < 1) return fail(ctx, USP_EINVAL, "n_avg must be >= 1");
+    if ((long long)pb->nx * pb->ny > (1LL << 26)) return fail(ctx, USP_EINVAL, "too many cells");
+    return USP_OK;
+}
+
+size_t footprint_of(const usp_problem* pb, const usp_numerics* nm, int nb)
+{
+    const size_t ncell = (size_t)pb->nx * pb->ny;
+    const size_t rb = nm->precision == 32 ? 4 : 8;
+    const size_t cap = (size_t)((nm->max_ppc + 63) / 64 * 64);
+    size_t b = 0;
+    b += 2 * (size_t)(pb->dim + 4) * ncell * cap * rb;  // particles
+    b += 2 * ncell * (size_t)(nb + 1) * 4;              // bin tables
+    b += 4 * NMOM * ncell * 8;                          // moments
+    b += 2 * ncell * 8 + ncell * 4 + 64;                // P_ne, counts, ctl
+    return b;
+}
+
+Instance* get_inst(usp_ctx* ctx, int id)
+{
+    if (!ctx || id < 0 || id >= (int)ctx->inst.size()) return nullptr;
+    Instance* in = ctx->inst[id];
+    return (in && in->alive) ? in : nullptr;
+}
+
+template <typename F>
+usp_status with_kernel(int prec, int dim, F f)
+{
+    if (prec == 32 && dim == 1) return f((float*)nullptr, std::integral_constant<int, 1>());
+    if (prec == 32 && dim == 2) return f((float*)nullptr, std::integral_constant<int, 2>());
+    if (prec == 64 && dim == 1) return f((double*)nullptr, std::integral_constant<int, 1>());
+    return f((double*)nullptr, std::integral_constant<int, 2>());
+}
+
+usp_status launch_cell(usp_ctx* ctx, const Batch& B, int prec, int dim, int max_nb, int nthreads)
+{
+    const size_t lds = lds_bytes(B.cap_lds, prec == 32 ? 4 : 8, dim, max_nb, nthreads);
+    return with_kernel(prec, dim, [&](auto* rp, auto dimc) -> usp_status {
+        using real = std::remove_pointer_t<decltype(rp)>;
+        constexpr int D = decltype(dimc)::value;
+        auto kern = cell_kernel<real, D>;
+        HIPCHK(ctx, hipFuncSetAttribute((const void*)kern,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(kern, dim3(B.ncells), dim3(nthreads), lds, ctx->stream, B);
+        HIPCHK(ctx, hipGetLastError());
+        return USP_OK;
+    });
+}
+
+usp_status launch_fields(usp_ctx* ctx, const Batch& B, int init)
+{
+    const int nt = 256;
+    hipLaunchKernelGGL(fields_kernel, dim3((B.ncells + nt - 1) / nt), dim3(nt), 0, ctx->stream, B,
+                       init);
+    HIPCHK(ctx, hipGetLastError());
+    return USP_OK;
+}
+
+usp_status launch_ctl(usp_ctx* ctx, const Batch& B, int relaxed)
+{
+    hipLaunchKernelGGL(ctl_kernel, dim3((B.ninst + 63) / 64), dim3(64), 0, ctx->stream, B,
+                       relaxed);
+    HIPCHK(ctx, hipGetLastError());
+    return USP_OK;
+}
+
+Batch single_batch(Instance* in, int mode)
+{
+    Batch B;
+    B.inst = in->d;
+    B.base = in->dbase;
+    B.ninst = 1;
+    B.ncells = in->h.ncell;
+    B.mode = mode;
+    B.cap_lds = in->h.cap;
+    return B;
+}
+
+usp_status upload_desc(usp_ctx* ctx, Instance* in)
+{
+    HIPCHK(ctx, hipMemcpyAsync(in->d, &in->h, sizeof(InstDev), hipMemcpyHostToDevice, ctx->stream));
+    return USP_OK;
+}
+
+usp_status read_ctl(usp_ctx* ctx, Instance* in, int* ctl)
+{
+    HIPCHK(ctx, hipMemcpyAsync(ctl, in->h.ctl, sizeof(int) * CTL_N, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return USP_OK;
+}
+
+usp_status err_status(usp_ctx* ctx, int e)
+{
+    if (e & ERR_CAPACITY) return fail(ctx, USP_ECAPACITY, "a cell exceeded max_ppc particles");
+    if (e & ERR_WINDOW)
+        return fail(ctx, USP_EWINDOW, "a particle moved farther than the sort window");
+    return USP_OK;
+}
+
+// moments of the current state + P_ne from them (initial / loaded states)
+usp_status finish_state(usp_ctx* ctx, Instance* in)
+{
+    Batch B = single_batch(in, MODE_MOMENTS);
+    usp_status s = launch_cell(ctx, B, in->h.prec, in->h.dim, in->h.nb, ctx->block);
+    if (s) return s;
+    if ((s = launch_fields(ctx, B, 1))) return s;
+    return launch_ctl(ctx, B, 0);
+}
+
+}  // namespace
+
+extern "C" {
+
+usp_status usp_create(const usp_device* dev, usp_ctx** out)
+{
+    if (!out) return USP_EINVAL;
+    usp_ctx* ctx = new usp_ctx();
+    if (dev) ctx->dev = *dev;
+    else memset(&ctx->dev, 0, sizeof(ctx->dev));
+    ctx->stream = (hipStream_t)ctx->dev.stream;
+    if (hipSetDevice(ctx->dev.device) != hipSuccess) {
+        delete ctx;
+        return USP_EDEVICE;
+    }
+    *out = ctx;
+    return USP_OK;
+}
+
+void usp_destroy(usp_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (size_t i = 0; i < ctx->inst.size(); ++i)
+        if (ctx->inst[i] && ctx->inst[i]->alive) usp_instance_free(ctx, (int)i);
+    for (Instance* in : ctx->inst) delete in;
+    if (ctx->bd) dfree(ctx, ctx->bd, sizeof(InstDev) * ctx->bcap);
+    if (ctx->bbase) dfree(ctx, ctx->bbase, sizeof(int) * (ctx->bcap + 1));
+    delete ctx;
+}
+
+const char* usp_last_error(usp_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+usp_status usp_footprint(const usp_problem* pb, const usp_numerics* nm, size_t* bytes_out)
+{
+    if (!pb || !nm || !bytes_out) return USP_EINVAL;
+    const int nb = pb->dim == 1 ? 255 : 225;
+    *bytes_out = footprint_of(pb, nm, nb);
+    return USP_OK;
+}
+
+usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb,
+                             const usp_numerics* nm, const double* init_n, const double* init_u,
+                             const double* init_T, int* id_out)
+{
+    if (!ctx) return USP_EINVAL;
+    usp_status s = validate(ctx, gas, pb, nm);
+    if (s) return s;
+    if (!init_n || !init_u || !init_T || !id_out) return fail(ctx, USP_EINVAL, "null init field");
+    HIPCHK(ctx, hipSetDevice(ctx->dev.device));
+    Instance* in = new Instance();
+    InstDev& h = in->h;
+    memset(&h, 0, sizeof(h));
+    h.m = gas->m;
+    h.kB = gas->kB;
+    h.mu_ref = gas->mu_ref;
+    h.T_ref = gas->T_ref;
+    h.omega = gas->omega;
+    h.Pr = gas->Pr;
+    h.R = gas->kB / gas->m;
+    h.F = gas->m * nm->Np / pb->vcell;
+    h.dim = pb->dim;
+    h.nx = pb->nx;
+    h.ny = pb->ny;
+    h.ncell = pb->nx * pb->ny;
+    h.x0 = pb->x0;
+    h.x1 = pb->x1;
+    h.y0 = pb->y0;
+    h.y1 = pb->y1;
+    h.dx = pb->dx;
+    h.dy = pb->dy;
+    h.inv_dx = pb->inv_dx;
+    h.inv_dy = pb->inv_dy;
+    h.vcell = pb->vcell;
+    h.Np = nm->Np;
+    for (int f = 0; f < 4; ++f) {
+        h.face_kind[f] = pb->face[f].kind;
+        h.face_T[f] = pb->face[f].T;
+        for (int k = 0; k < 3; ++k) h.face_u[3 * f + k] = pb->face[f].u[k];
+    }
+    for (int k = 0; k < 3; ++k) h.accel[k] = pb->accel[k];
+    h.dt = nm->dt;
+    h.r_p = nm->r_p;
+    h.Kn_c = nm->Kn_c;
+    h.pne_fixed = nm->pne_fixed;
+    h.pne_mode = nm->pne_mode;
+    h.n_avg = nm->n_avg;
+    h.avg_start = nm->avg_start;
+    h.prec = nm->precision;
+    h.weight_mode = nm->weight_mode;
+    h.conserve_mode = nm->conserve_mode;
+    h.max_ppc = nm->max_ppc;
+    h.jmom_mode = nm->jmom_mode;
+    h.proj = nm->spawn_projection;
+    h.key0 = (uint32_t)(nm->seed & 0xFFFFFFFFu);
+    h.key1 = (uint32_t)(nm->seed >> 32);
+    Window w = choose_window(gas, pb, nm, init_u, init_T);
+    h.Kx = w.Kx;
+    h.Ky = w.Ky;
+    h.nbx = 2 * w.Kx + 1;
+    h.nb = (2 * w.Ky + 1) * h.nbx;
+    h.cap = (nm->max_ppc + 63) / 64 * 64;
+
+    const size_t ncell = (size_t)h.ncell;
+    const size_t rb = h.prec == 32 ? 4 : 8;
+    auto A = [&](size_t bytes) -> void* {
+        void* p = dalloc(ctx, bytes);
+        if (p) {
+            in->allocs.push_back(p);
+            in->bytes += bytes;
+        }
+        return p;
+    };
+    bool ok = true;
+    for (int b = 0; b < 2; ++b) {
+        for (int k = 0; k < 6; ++k) {
+            if (k == 0 && h.dim == 1) {
+                h.pc[b][k] = nullptr;
+                continue;
+            }
+            h.pc[b][k] = A(ncell * h.cap * rb);
+            ok = ok && h.pc[b][k];
+        }
+        h.tab[b] = (uint32_t*)A(ncell * (h.nb + 1) * 4);
+        ok = ok && h.tab[b];
+    }
+    h.mom = (double*)A(NMOM * ncell * 8);
+    h.raw = (double*)A(NMOM * ncell * 8);
+    h.avg = (double*)A(NMOM * ncell * 8);
+    h.avgs = (double*)A(NMOM * ncell * 8);
+    h.pcur = (double*)A(ncell * 8);
+    h.pprev = (double*)A(ncell * 8);
+    h.cnt = (int*)A(ncell * 4);
+    h.ctl = (int*)A(CTL_N * 4);
+    in->d = (InstDev*)A(sizeof(InstDev));
+    in->dbase = (int*)A(2 * sizeof(int));
+    ok = ok && h.mom && h.raw && h.avg && h.avgs && h.pcur && h.pprev && h.cnt && h.ctl && in->d &&
+         in->dbase;
+    if (!ok) {
+        for (void* p : in->allocs) dfree(ctx, p, 0);
+        ctx->allocated -= std::min(ctx->allocated, in->bytes);
+        delete in;
+        return fail(ctx, USP_ENOMEM, "device allocation failed or over budget");
+    }
+    HIPCHK(ctx, hipMemsetAsync(h.avg, 0, NMOM * ncell * 8, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(h.avgs, 0, NMOM * ncell * 8, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(h.ctl, 0, CTL_N * 4, ctx->stream));
+    int base[2] = {0, h.ncell};
+    HIPCHK(ctx, hipMemcpyAsync(in->dbase, base, sizeof(base), hipMemcpyHostToDevice, ctx->stream));
+    if ((s = upload_desc(ctx, in))) return s;
+
+    // Table 2 step 1
+    double *dn = nullptr, *du = nullptr, *dT = nullptr;
+    HIPCHK(ctx, hipMalloc(&dn, ncell * 8));
+    HIPCHK(ctx, hipMalloc(&du, 3 * ncell * 8));
+    HIPCHK(ctx, hipMalloc(&dT, ncell * 8));
+    HIPCHK(ctx, hipMemcpyAsync(dn, init_n, ncell * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(du, init_u, 3 * ncell * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(dT, init_T, ncell * 8, hipMemcpyHostToDevice, ctx->stream));
+    Batch B = single_batch(in, MODE_MOMENTS);
+    s = with_kernel(h.prec, h.dim, [&](auto* rp, auto dimc) -> usp_status {
+        using real = std::remove_pointer_t<decltype(rp)>;
+        constexpr int D = decltype(dimc)::value;
+        hipLaunchKernelGGL((init_kernel<real, D>), dim3(h.ncell), dim3(256), 0, ctx->stream, B, dn,
+                           du, dT);
+        HIPCHK(ctx, hipGetLastError());
+        return USP_OK;
+    });
+    if (s) return s;
+    if ((s = finish_state(ctx, in))) return s;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipFree(dn);
+    (void)hipFree(du);
+    (void)hipFree(dT);
+    in->alive = true;
+    ctx->inst.push_back(in);
+    *id_out = (int)ctx->inst.size() - 1;
+    ctx->last_ids.clear();
+    int ctl[CTL_N];
+    if ((s = read_ctl(ctx, in, ctl))) return s;
+    return err_status(ctx, ctl[CTL_ERR]);
+}
+
+usp_status usp_instance_free(usp_ctx* ctx, int id)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in) return fail(ctx, USP_ESTATE, "unknown instance");
+    (void)hipStreamSynchronize(ctx->stream);
+    for (void* p : in->allocs) dfree(ctx, p, 0);
+    ctx->allocated -= std::min(ctx->allocated, in->bytes);
+    in->allocs.clear();
+    in->alive = false;
+    ctx->last_ids.clear();
+    return USP_OK;
+}
+
+usp_status usp_set_block(usp_ctx* ctx, int threads)
+{
+    if (!ctx) return USP_EINVAL;
+    if (threads == 0) threads = 256;
+    if (threads < 64 || threads > 256 || threads % 64)
+        return fail(ctx, USP_EINVAL, "threads must be a multiple of 64 in [64, 256]");
+    ctx->block = threads;
+    return USP_OK;
+}
+
+usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps)
+{
+    if (!ctx || !ids || n_ids <= 0) return fail(ctx, USP_EINVAL, "no instances");
+    if (nsteps <= 0) return USP_OK;
+    // group the instances by kernel flavour (precision, dimension)
+    for (int g = 0; g < 4; ++g) {
+        const int prec = g < 2 ? 32 : 64, dim = (g & 1) ? 2 : 1;
+        std::vector<int> sel;
+        for (int i = 0; i < n_ids; ++i) {
+            Instance* in = get_inst(ctx, ids[i]);
+            if (!in) return fail(ctx, USP_ESTATE, "unknown or freed instance in step");
+            if (in->h.prec == prec && in->h.dim == dim) sel.push_back(ids[i]);
+        }
+        if (sel.empty()) continue;
+        // descriptor array of this group (cached while the group is unchanged)
+        std::vector<int> key = sel;
+        key.push_back(-1 - g);
+        if (key != ctx->last_ids) {
+            if ((int)sel.size() > ctx->bcap) {
+                if (ctx->bd) dfree(ctx, ctx->bd, sizeof(InstDev) * ctx->bcap);
+                if (ctx->bbase) dfree(ctx, ctx->bbase, sizeof(int) * (ctx->bcap + 1));
+                ctx->bcap = std::max((int)sel.size(), 16);
+                ctx->bd = (InstDev*)dalloc(ctx, sizeof(InstDev) * ctx->bcap);
+                ctx->bbase = (int*)dalloc(ctx, sizeof(int) * (ctx->bcap + 1));
+                if (!ctx->bd || !ctx->bbase) return fail(ctx, USP_ENOMEM, "batch table");
+            }
+            std::vector<InstDev> hd;
+            std::vector<int> base(1, 0);
+            for (int id : sel) {
+                hd.push_back(ctx->inst[id]->h);
+                base.push_back(base.back() + ctx->inst[id]->h.ncell);
+            }
+            HIPCHK(ctx, hipMemcpyAsync(ctx->bd, hd.data(), sizeof(InstDev) * hd.size(),
+                                       hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(ctx, hipMemcpyAsync(ctx->bbase, base.data(), sizeof(int) * base.size(),
+                                       hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            ctx->last_ids = key;
+        }
+        Batch B;
+        B.inst = ctx->bd;
+        B.base = ctx->bbase;
+        B.ninst = (int)sel.size();
+        B.ncells = 0;
+        B.cap_lds = 0;
+        int max_nb = 0;
+        for (int id : sel) {
+            B.ncells += ctx->inst[id]->h.ncell;
+            B.cap_lds = std::max(B.cap_lds, ctx->inst[id]->h.cap);
+            max_nb = std::max(max_nb, ctx->inst[id]->h.nb);
+        }
+        usp_status s;
+        B.mode = MODE_MOVE;
+        if ((s = launch_cell(ctx, B, prec, dim, max_nb, ctx->block))) return s;
+        if ((s = launch_ctl(ctx, B, 0))) return s;
+        for (int k = 0; k < nsteps; ++k) {
+            B.mode = k + 1 < nsteps ? (MODE_RELAX | MODE_MOVE) : MODE_RELAX;
+            if ((s = launch_cell(ctx, B, prec, dim, max_nb, ctx->block))) return s;
+            if ((s = launch_fields(ctx, B, 0))) return s;
+            if ((s = launch_ctl(ctx, B, 1))) return s;
+        }
+    }
+    return USP_OK;
+}
+
+usp_status usp_sync(usp_ctx* ctx)
+{
+    if (!ctx) return USP_EINVAL;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (size_t i = 0; i < ctx->inst.size(); ++i) {
+        Instance* in = ctx->inst[i];
+        if (!in || !in->alive) continue;
+        int ctl[CTL_N];
+        usp_status s = read_ctl(ctx, in, ctl);
+        if (s) return s;
+        if (ctl[CTL_ERR]) return err_status(ctx, ctl[CTL_ERR]);
+    }
+    return USP_OK;
+}
+
+usp_status usp_instance_status(usp_ctx* ctx, int id)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in) return fail(ctx, USP_ESTATE, "unknown instance");
+    int ctl[CTL_N];
+    usp_status s = read_ctl(ctx, in, ctl);
+    if (s) return s;
+    return err_status(ctx, ctl[CTL_ERR]);
+}
+
+usp_status usp_num_cells(usp_ctx* ctx, int id, int* ncell)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in || !ncell) return fail(ctx, USP_ESTATE, "unknown instance");
+    *ncell = in->h.ncell;
+    return USP_OK;
+}
+
+usp_status usp_num_particles(usp_ctx* ctx, int id, long long* n)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in || !n) return fail(ctx, USP_ESTATE, "unknown instance");
+    std::vector<int> cnt(in->h.ncell);
+    HIPCHK(ctx, hipMemcpyAsync(cnt.data(), in->h.cnt, sizeof(int) * cnt.size(),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    long long t = 0;
+    for (int c : cnt) t += c;
+    *n = t;
+    return USP_OK;
+}
+
+usp_status usp_get_state(usp_ctx* ctx, int id, int* counts, double* parts, double* cells,
+                         int* step, int* n_samples)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in) return fail(ctx, USP_ESTATE, "unknown instance");
+    const InstDev& h = in->h;
+    int ctl[CTL_N];
+    usp_status s = read_ctl(ctx, in, ctl);
+    if (s) return s;
+    const int cur = ctl[CTL_CUR];
+    const size_t ncell = (size_t)h.ncell, nb1 = (size_t)h.nb + 1;
+    std::vector<uint32_t> tab(ncell * nb1);
+    HIPCHK(ctx, hipMemcpy(tab.data(), h.tab[cur], tab.size() * 4, hipMemcpyDeviceToHost));
+    if (counts)
+        for (size_t c = 0; c < ncell; ++c) counts[c] = (int)tab[c * nb1 + h.nb];
+    if (parts) {
+        const size_t rb = h.prec == 32 ? 4 : 8;
+        std::vector<unsigned char> buf(ncell * h.cap * rb);
+        long long k0 = 0;
+        std::vector<long long> off(ncell + 1, 0);
+        for (size_t c = 0; c < ncell; ++c) off[c + 1] = off[c] + tab[c * nb1 + h.nb];
+        for (int comp = 0; comp < 6; ++comp) {
+            if (!h.pc[cur][comp]) {
+                for (long long i = 0; i < off[ncell]; ++i) parts[6 * i + comp] = 0.0;
+                continue;
+            }
+            HIPCHK(ctx, hipMemcpy(buf.data(), h.pc[cur][comp], buf.size(), hipMemcpyDeviceToHost));
+            for (size_t c = 0; c < ncell; ++c) {
+                const long long n = off[c + 1] - off[c];
+                for (long long j = 0; j < n; ++j) {
+                    const size_t src = c * h.cap + j;
+                    const double v = h.prec == 32 ? (double)((float*)buf.data())[src]
+                                                  : ((double*)buf.data())[src];
+                    parts[6 * (off[c] + j) + comp] = v;
+                }
+            }
+        }
+        (void)k0;
+    }
+    if (cells) {
+        std::vector<double> a(NMOM * ncell);
+        double* arrs[4] = {h.mom, h.raw, h.avg, h.avgs};
+        for (int q = 0; q < 4; ++q) {
+            HIPCHK(ctx, hipMemcpy(a.data(), arrs[q], a.size() * 8, hipMemcpyDeviceToHost));
+            for (size_t c = 0; c < ncell; ++c)
+                for (int k = 0; k < NMOM; ++k) cells[c * (4 * NMOM + 2) + q * NMOM + k] = a[k * ncell + c];
+        }
+        std::vector<double> p(ncell);
+        HIPCHK(ctx, hipMemcpy(p.data(), h.pcur, ncell * 8, hipMemcpyDeviceToHost));
+        for (size_t c = 0; c < ncell; ++c) cells[c * (4 * NMOM + 2) + 4 * NMOM] = p[c];
+        HIPCHK(ctx, hipMemcpy(p.data(), h.pprev, ncell * 8, hipMemcpyDeviceToHost));
+        for (size_t c = 0; c < ncell; ++c) cells[c * (4 * NMOM + 2) + 4 * NMOM + 1] = p[c];
+    }
+    if (step) *step = ctl[CTL_STEP];
+    if (n_samples) *n_samples = ctl[CTL_NSAMP];
+    return err_status(ctx, ctl[CTL_ERR]);
+}
+
+usp_status usp_set_state(usp_ctx* ctx, int id, const int* counts, const double* parts,
+                         const double* cells, int step, int n_samples)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in || !counts || !parts) return fail(ctx, USP_EINVAL, "bad set_state arguments");
+    const InstDev& h = in->h;
+    int ctl[CTL_N];
+    usp_status s = read_ctl(ctx, in, ctl);
+    if (s) return s;
+    const int cur = ctl[CTL_CUR];
+    const size_t ncell = (size_t)h.ncell, nb1 = (size_t)h.nb + 1;
+    for (size_t c = 0; c < ncell; ++c)
+        if (counts[c] < 0 || counts[c] > h.max_ppc)
+            return fail(ctx, USP_ECAPACITY, "a cell holds more than max_ppc particles");
+    std::vector<long long> off(ncell + 1, 0);
+    for (size_t c = 0; c < ncell; ++c) off[c + 1] = off[c] + counts[c];
+    const size_t rb = h.prec == 32 ? 4 : 8;
+    std::vector<unsigned char> buf(ncell * h.cap * rb, 0);
+    for (int comp = 0; comp < 6; ++comp) {
+        if (!h.pc[cur][comp]) continue;
+        for (size_t c = 0; c < ncell; ++c)
+            for (long long j = 0; j < counts[c]; ++j) {
+                const double v = parts[6 * (off[c] + j) + comp];
+                const size_t dst = c * h.cap + j;
+                if (h.prec == 32) ((float*)buf.data())[dst] = (float)v;
+                else ((double*)buf.data())[dst] = v;
+            }
+        HIPCHK(ctx, hipMemcpy(h.pc[cur][comp], buf.data(), buf.size(), hipMemcpyHostToDevice));
+    }
+    std::vector<uint32_t> tab(ncell * nb1);
+    const int centre = h.Ky * h.nbx + h.Kx;
+    for (size_t c = 0; c < ncell; ++c)
+        for (int b = 0; b <= h.nb; ++b) tab[c * nb1 + b] = b <= centre ? 0u : (uint32_t)counts[c];
+    HIPCHK(ctx, hipMemcpy(h.tab[cur], tab.data(), tab.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(h.cnt, counts, ncell * 4, hipMemcpyHostToDevice));
+    int nctl[CTL_N] = {cur, step, cells ? n_samples : 0, 0};
+    HIPCHK(ctx, hipMemcpy(h.ctl, nctl, sizeof(nctl), hipMemcpyHostToDevice));
+    if (cells) {
+        std::vector<double> a(NMOM * ncell);
+        double* arrs[4] = {h.mom, h.raw, h.avg, h.avgs};
+        for (int q = 0; q < 4; ++q) {
+            for (size_t c = 0; c < ncell; ++c)
+                for (int k = 0; k < NMOM; ++k) a[k * ncell + c] = cells[c * (4 * NMOM + 2) + q * NMOM + k];
+            HIPCHK(ctx, hipMemcpy(arrs[q], a.data(), a.size() * 8, hipMemcpyHostToDevice));
+        }
+        std::vector<double> p(ncell);
+        for (size_t c = 0; c < ncell; ++c) p[c] = cells[c * (4 * NMOM + 2) + 4 * NMOM];
+        HIPCHK(ctx, hipMemcpy(h.pcur, p.data(), ncell * 8, hipMemcpyHostToDevice));
+        for (size_t c = 0; c < ncell; ++c) p[c] = cells[c * (4 * NMOM + 2) + 4 * NMOM + 1];
+        HIPCHK(ctx, hipMemcpy(h.pprev, p.data(), ncell * 8, hipMemcpyHostToDevice));
+        return USP_OK;
+    }
+    HIPCHK(ctx, hipMemset(h.avg, 0, NMOM * ncell * 8));
+    HIPCHK(ctx, hipMemset(h.avgs, 0, NMOM * ncell * 8));
+    if ((s = finish_state(ctx, in))) return s;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return USP_OK;
+}
+
+usp_status usp_get_fields(usp_ctx* ctx, int id, int which, double* out)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in || !out) return fail(ctx, USP_EINVAL, "bad get_fields arguments");
+    const size_t ncell = (size_t)in->h.ncell;
+    double* d = nullptr;
+    HIPCHK(ctx, hipMalloc(&d, ncell * 18 * 8));
+    Batch B = single_batch(in, 0);
+    hipLaunchKernelGGL(fields_out_kernel, dim3((ncell + 255) / 256), dim3(256), 0, ctx->stream, B,
+                       which, d);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipMemcpyAsync(out, d, ncell * 18 * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipFree(d);
+    return USP_OK;
+}
+
+usp_status usp_set_diag(usp_ctx* ctx, int id, int on)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in) return fail(ctx, USP_ESTATE, "unknown instance");
+    if (on && !in->h.diag) {
+        in->h.diag = (double*)dalloc(ctx, (size_t)in->h.ncell * NDIAG * 8);
+        if (!in->h.diag) return fail(ctx, USP_ENOMEM, "diag buffer");
+        in->allocs.push_back(in->h.diag);
+        in->bytes += (size_t)in->h.ncell * NDIAG * 8;
+        HIPCHK(ctx, hipMemsetAsync(in->h.diag, 0, (size_t)in->h.ncell * NDIAG * 8, ctx->stream));
+    } else if (!on) {
+        in->h.diag = nullptr;
+    }
+    ctx->last_ids.clear();
+    return upload_desc(ctx, in);
+}
+
+usp_status usp_get_diag(usp_ctx* ctx, int id, double* out)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in || !out || !in->h.diag) return fail(ctx, USP_ESTATE, "diagnostics not enabled");
+    HIPCHK(ctx, hipMemcpyAsync(out, in->h.diag, (size_t)in->h.ncell * NDIAG * 8,
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return USP_OK;
+}
+
+usp_status usp_philox(usp_ctx* ctx, const uint32_t* ctr, uint32_t k0, uint32_t k1, int n,
+                      uint32_t* out)
+{
+    if (!ctx || !ctr || !out || n <= 0) return USP_EINVAL;
+    uint32_t *dc = nullptr, *dout = nullptr;
+    HIPCHK(ctx, hipMalloc(&dc, (size_t)n * 16));
+    HIPCHK(ctx, hipMalloc(&dout, (size_t)n * 16));
+    HIPCHK(ctx, hipMemcpy(dc, ctr, (size_t)n * 16, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(philox_kernel, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, dc, k0, k1,
+                       n, dout);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    HIPCHK(ctx, hipMemcpy(out, dout, (size_t)n * 16, hipMemcpyDeviceToHost));
+    (void)hipFree(dc);
+    (void)hipFree(dout);
+    return USP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,312 @@
+"""ctypes binding of libusp (include/usp.h): argument marshalling only.
+
+Every step of the solver runs in the HIP kernels of ``libusp.so``; this module
+converts a :class:`paper_1808_03801_amd.problems.Problem` into the C structs,
+hands PyTorch's caching allocator and current stream to the library, and
+copies states in and out.  It raises if the library or the GPU is missing:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libusp.so")
+
+NMOM = 13
+NCS = 4 * NMOM + 2
+NF = 18
+NDIAG = 32
+
+STATUS = {0: "USP_OK", -1: "USP_EINVAL", -2: "USP_ENOMEM", -3: "USP_ECAPACITY",
+          -4: "USP_EWINDOW", -5: "USP_EDEVICE", -7: "USP_ESTATE", -8: "USP_ENOLIB"}
+
+
+class UspError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Gas(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("m", "kB", "mu_ref", "T_ref", "omega", "Pr")]
+
+
+class Face(C.Structure):
+    _fields_ = [("kind", C.c_int), ("T", C.c_double), ("u", C.c_double * 3)]
+
+
+class ProblemC(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int)] + \
+               [(n, C.c_double) for n in ("x0", "x1", "y0", "y1", "dx", "dy", "inv_dx",
+                                          "inv_dy", "vcell")] + \
+               [("face", Face * 4), ("accel", C.c_double * 3)]
+
+
+class Numerics(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("dt", "Np", "r_p", "Kn_c", "pne_fixed")] + \
+               [(n, C.c_int) for n in ("pne_mode", "n_avg", "avg_start", "precision",
+                                       "weight_mode", "conserve_mode", "max_ppc", "jmom_mode",
+                                       "spawn_projection", "window")] + \
+               [("seed", C.c_uint64)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class Device(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p),
+                ("stream", C.c_void_p), ("device", C.c_int), ("budget", C.c_size_t)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libusp.so (built by paper_1808_03801_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1808_03801_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
+        u32p = C.POINTER(C.c_uint32)
+        sig = {
+            "usp_create": (C.c_int, [C.POINTER(Device), C.POINTER(vp)]),
+            "usp_destroy": (None, [vp]),
+            "usp_last_error": (C.c_char_p, [vp]),
+            "usp_footprint": (C.c_int, [C.POINTER(ProblemC), C.POINTER(Numerics),
+                                        C.POINTER(C.c_size_t)]),
+            "usp_instance_init": (C.c_int, [vp, C.POINTER(Gas), C.POINTER(ProblemC),
+                                            C.POINTER(Numerics), dp, dp, dp, ip]),
+            "usp_instance_free": (C.c_int, [vp, C.c_int]),
+            "usp_step": (C.c_int, [vp, ip, C.c_int, C.c_int]),
+            "usp_sync": (C.c_int, [vp]),
+            "usp_instance_status": (C.c_int, [vp, C.c_int]),
+            "usp_num_cells": (C.c_int, [vp, C.c_int, ip]),
+            "usp_num_particles": (C.c_int, [vp, C.c_int, C.POINTER(C.c_longlong)]),
+            "usp_get_state": (C.c_int, [vp, C.c_int, ip, dp, dp, ip, ip]),
+            "usp_set_state": (C.c_int, [vp, C.c_int, ip, dp, dp, C.c_int, C.c_int]),
+            "usp_get_fields": (C.c_int, [vp, C.c_int, C.c_int, dp]),
+            "usp_set_diag": (C.c_int, [vp, C.c_int, C.c_int]),
+            "usp_get_diag": (C.c_int, [vp, C.c_int, dp]),
+            "usp_set_block": (C.c_int, [vp, C.c_int]),
+            "usp_philox": (C.c_int, [vp, u32p, C.c_uint32, C.c_uint32, C.c_int, u32p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    """names the C header declares (for the load check)"""
+    return ["usp_create", "usp_destroy", "usp_last_error", "usp_footprint", "usp_instance_init",
+            "usp_instance_free", "usp_step", "usp_sync", "usp_instance_status", "usp_num_cells",
+            "usp_num_particles", "usp_get_state", "usp_set_state", "usp_get_fields",
+            "usp_set_diag", "usp_get_diag", "usp_set_block", "usp_philox"]
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def to_c(pb):
+    """(Gas, ProblemC, Numerics) of a problems.Problem"""
+    g = pb.gas
+    gas = Gas(g.m, g.kB, g.mu_ref, g.T_ref, g.omega, g.Pr)
+    p = ProblemC()
+    p.dim, p.nx, p.ny = pb.dim, pb.nx, pb.ny
+    for n in ("x0", "x1", "y0", "y1", "dx", "dy", "inv_dx", "inv_dy", "vcell"):
+        setattr(p, n, getattr(pb, n))
+    for i, f in enumerate(pb.faces):
+        p.face[i].kind = f.kind
+        p.face[i].T = f.T
+        for k in range(3):
+            p.face[i].u[k] = f.u[k]
+    for k in range(3):
+        p.accel[k] = pb.accel[k]
+    nm = Numerics()
+    for n in ("dt", "Np", "r_p", "Kn_c", "pne_fixed"):
+        setattr(nm, n, getattr(pb, n))
+    for n in ("pne_mode", "n_avg", "avg_start", "precision", "weight_mode", "conserve_mode",
+              "max_ppc", "jmom_mode", "spawn_projection"):
+        setattr(nm, n, int(getattr(pb, n)))
+    nm.window = int(pb.meta.get("window", 0))
+    nm.seed = int(pb.seed)
+    return gas, p, nm
+
+
+def footprint(pb) -> int:
+    _, p, nm = to_c(pb)
+    out = C.c_size_t()
+    _check(None, lib().usp_footprint(C.byref(p), C.byref(nm), C.byref(out)))
+    return out.value
+
+
+def _check(ctx, status):
+    if status != 0:
+        msg = lib().usp_last_error(ctx).decode() if ctx else ""
+        raise UspError(status, msg)
+
+
+class State:
+    """Host copy of a solver state (same layout as the C-ABI)."""
+
+    def __init__(self, counts, parts, cells, step, n_samples):
+        self.counts = np.ascontiguousarray(counts, dtype=np.int32)
+        self.parts = np.ascontiguousarray(parts, dtype=np.float64).reshape(-1, 6)
+        self.cells = None if cells is None else np.ascontiguousarray(cells, dtype=np.float64)
+        self.step = int(step)
+        self.n_samples = int(n_samples)
+
+    @property
+    def offsets(self):
+        return np.concatenate([[0], np.cumsum(self.counts)])
+
+
+class Context:
+    """One device + stream.  By default device memory comes from PyTorch's
+    caching allocator and work goes on PyTorch's current stream."""
+
+    def __init__(self, device: int = 0, use_torch: bool = True, budget: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libusp needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.device = device
+        self._live = {}
+        dev = Device()
+        dev.device = device
+        dev.budget = budget
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        dev.stream = C.c_void_p(stream.cuda_stream)
+        if use_torch:
+            def _alloc(nbytes, user):
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+                self._live[ptr] = nbytes
+                return ptr
+
+            def _free(ptr, user):
+                if ptr in self._live:
+                    del self._live[ptr]
+                    torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc_cb = ALLOC_FN(_alloc)
+            self._free_cb = FREE_FN(_free)
+            dev.alloc = self._alloc_cb
+            dev.free = self._free_cb
+        h = C.c_void_p()
+        _check(None, lib().usp_create(C.byref(dev), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().usp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, pb) -> "Instance":
+        gas, p, nm = to_c(pb)
+        n = np.ascontiguousarray(pb.init_n, dtype=np.float64)
+        u = np.ascontiguousarray(pb.init_u, dtype=np.float64).reshape(-1)
+        T = np.ascontiguousarray(pb.init_T, dtype=np.float64)
+        iid = C.c_int()
+        _check(self.h, lib().usp_instance_init(self.h, C.byref(gas), C.byref(p), C.byref(nm),
+                                              _dp(n), _dp(u), _dp(T), C.byref(iid)))
+        return Instance(self, iid.value, pb)
+
+    def step(self, instances, nsteps: int = 1):
+        ids = np.array([i.id for i in instances], dtype=np.int32)
+        _check(self.h, lib().usp_step(self.h, _ip(ids), len(ids), int(nsteps)))
+
+    def sync(self):
+        _check(self.h, lib().usp_sync(self.h))
+
+    def set_block(self, threads: int):
+        _check(self.h, lib().usp_set_block(self.h, int(threads)))
+
+    def philox(self, ctr, key):
+        ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+        out = np.zeros_like(ctr)
+        u32p = C.POINTER(C.c_uint32)
+        _check(self.h, lib().usp_philox(self.h, ctr.ctypes.data_as(u32p), int(key[0]),
+                                        int(key[1]), ctr.shape[0], out.ctypes.data_as(u32p)))
+        return out
+
+
+class Instance:
+    def __init__(self, ctx: Context, iid: int, pb):
+        self.ctx = ctx
+        self.id = iid
+        self.pb = pb
+        self.ncell = pb.nx * pb.ny
+
+    def step(self, nsteps: int = 1):
+        self.ctx.step([self], nsteps)
+
+    def status(self) -> int:
+        return lib().usp_instance_status(self.ctx.h, self.id)
+
+    def num_particles(self) -> int:
+        n = C.c_longlong()
+        _check(self.ctx.h, lib().usp_num_particles(self.ctx.h, self.id, C.byref(n)))
+        return n.value
+
+    def get_state(self, with_parts=True) -> State:
+        counts = np.zeros(self.ncell, np.int32)
+        L = lib()
+        st, ns = C.c_int(), C.c_int()
+        _check(self.ctx.h, L.usp_get_state(self.ctx.h, self.id, _ip(counts), None, None,
+                                           C.byref(st), C.byref(ns)))
+        N = int(counts.sum())
+        parts = np.zeros((max(N, 1), 6))
+        cells = np.zeros((self.ncell, NCS))
+        _check(self.ctx.h, L.usp_get_state(self.ctx.h, self.id, _ip(counts),
+                                           _dp(parts) if with_parts else None, _dp(cells),
+                                           C.byref(st), C.byref(ns)))
+        return State(counts, parts[:N], cells, st.value, ns.value)
+
+    def set_state(self, s):
+        parts = np.ascontiguousarray(s.parts, dtype=np.float64).reshape(-1, 6)
+        if parts.shape[0] == 0:
+            parts = np.zeros((1, 6))
+        counts = np.ascontiguousarray(s.counts, dtype=np.int32)
+        cells = None if s.cells is None else np.ascontiguousarray(s.cells, dtype=np.float64)
+        _check(self.ctx.h, lib().usp_set_state(self.ctx.h, self.id, _ip(counts), _dp(parts),
+                                               None if cells is None else _dp(cells),
+                                               int(s.step), int(s.n_samples)))
+
+    def fields(self, which: int = 0):
+        out = np.zeros((self.ncell, NF))
+        _check(self.ctx.h, lib().usp_get_fields(self.ctx.h, self.id, which, _dp(out)))
+        return out
+
+    def set_diag(self, on=True):
+        _check(self.ctx.h, lib().usp_set_diag(self.ctx.h, self.id, int(on)))
+
+    def diag(self):
+        out = np.zeros((self.ncell, NDIAG))
+        _check(self.ctx.h, lib().usp_get_diag(self.ctx.h, self.id, _dp(out)))
+        return out
+
+    def free(self):
+        _check(self.ctx.h, lib().usp_instance_free(self.ctx.h, self.id))

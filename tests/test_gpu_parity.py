@@ -1,0 +1,180 @@
+"""GPU (libusp, gfx950) against the CPU oracle.
+
+Every input state is produced by the oracle; the HIP path only ever
+receives it.  See tests/parity_util.py for the comparison protocol."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1808_03801_amd import problems as P
+from tests.parity_util import compare_step
+from tests.philox_ref import philox4
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    """CPU check: libusp.so loads and exports each function of include/usp.h"""
+    import ctypes
+    from paper_1808_03801_amd import usp
+    if not os.path.exists(usp.LIB_PATH):
+        pytest.skip("libusp.so not built")
+    hdr = open(os.path.join(ROOT, "include", "usp.h")).read()
+    names = sorted(set(re.findall(r"\b(usp_[a-z_]+)\s*\(", hdr)))
+    assert len(names) >= 15
+    L = ctypes.CDLL(usp.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(usp.exported_symbols()) == set(names)
+
+
+def _gpu():
+    from paper_1808_03801_amd import usp
+    return usp
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    usp = _gpu()
+    c = usp.Context(0)
+    yield c
+    c.close()
+
+
+def _cases():
+    return {
+        "c1_couette_fp64": lambda: P.couette_1d(ncell=40, ppc=100, seed=3),
+        "couette_fp32_avg": lambda: P.couette_1d(ncell=60, ppc=120, Kn=0.02, U_w=150.0,
+                                                 dt_over_tau=3.0, precision=32, seed=4).replace(
+            jmom_mode=P.JMOM_AVG, spawn_projection=1),
+        "thermal_couette_fp32": lambda: P.thermal_couette_1d(ncell=120, ppc=200, Kn=1e-2,
+                                                             seed=5),
+        "sod_fp32": lambda: P.sod_1d(ncell=150, mean_ppc=200, seed=6),
+        "cavity_fp32": lambda: P.cavity_2d(Kn=0.01, n=16, ppc=80, seed=7),
+        "box_periodic_fp64": lambda: P.homogeneous_box(ncell=9, ppc=400, nu_dt=2.0, pne=0.7,
+                                                       precision=64, seed=8),
+        "poiseuille_fp32": lambda: P.poiseuille_1d(Kn=0.01, dpdx=1.6e8, ncell=50, ppc=200,
+                                                   dt_over_tau=2.0, seed=9),
+    }
+
+
+@pytest.mark.gpu
+def test_device_philox_matches_reference(ctx):
+    rng = np.random.default_rng(12)
+    ctr = rng.integers(0, 2**32, (4096, 4), dtype=np.uint64).astype(np.uint32)
+    key = [0x12345678, 0x9ABCDEF0]
+    out = ctx.philox(ctr, key)
+    for i in range(0, 4096, 37):
+        assert list(out[i]) == philox4([int(x) for x in ctr[i]], key)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", list(_cases().keys()))
+def test_initial_state_parity(ctx, name):
+    pb = _cases()[name]()
+    o = O.Oracle(pb)
+    g = ctx.add(pb)
+    so, sg = o.get_state(), g.get_state()
+    assert np.array_equal(so.counts, sg.counts)
+    # positions and velocities are double computations rounded once on both
+    # sides; weights are 1
+    tol = 1e-12 if pb.precision == 64 else 0.0
+    dpos = np.abs(so.parts[:, :2] - sg.parts[:, :2]).max()
+    assert dpos <= tol * max(pb.y1, pb.x1)
+    dvel = np.abs(so.parts[:, 2:5] - sg.parts[:, 2:5]).max()
+    assert dvel <= (1e-9 if pb.precision == 64 else 1e-4)
+    fo, fg = o.fields(0), g.fields(0)
+    assert np.allclose(fo[:, :16], fg[:, :16], rtol=1e-10, atol=1e-10 * np.abs(fo[:, 6]).max())
+    assert np.allclose(fo[:, 16], fg[:, 16], rtol=1e-9, atol=1e-12)
+    g.free()
+
+
+def _oracle_state(pb, warm):
+    o = O.Oracle(pb)
+    o.step(warm)
+    assert o.error == 0
+    return o.get_state()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", list(_cases().keys()))
+def test_single_step_parity(ctx, name):
+    pb = _cases()[name]()
+    st = _oracle_state(pb, 3)
+    o = O.Oracle(pb)
+    o.set_state(st)
+    g = ctx.add(pb)
+    g.set_diag(True)
+    g.set_state(st)
+    o.step(1)
+    g.step(1)
+    ctx.sync()
+    rep = {}
+    compare_step(pb, o.get_state(), g.get_state(), o.diag(), g.diag(), o.fields(0),
+                 g.fields(0), report=rep)
+    print(name, rep)
+    g.free()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["c1_couette_fp64", "thermal_couette_fp32", "cavity_fp32"])
+def test_multi_step_trajectory(ctx, name):
+    """several steps in one call (fused relax + move kernel) against the
+    oracle stepping the same number of times; compared while no decision has
+    flipped, i.e. cell counts still agree"""
+    pb = _cases()[name]()
+    st = _oracle_state(pb, 2)
+    o = O.Oracle(pb)
+    o.set_state(st)
+    g = ctx.add(pb)
+    g.set_diag(True)
+    g.set_state(st)
+    o.step(3)
+    g.step(3)
+    ctx.sync()
+    so, sg = o.get_state(), g.get_state()
+    same = so.counts == sg.counts
+    assert same.mean() > 0.97, same.mean()
+    fo, fg = o.fields(0), g.fields(0)
+    p = fo[:, 6]
+    rel_rho = np.abs(fg[same, 1] - fo[same, 1]) / fo[same, 1]
+    assert np.median(rel_rho) < 1e-5
+    g.free()
+
+
+@pytest.mark.gpu
+def test_steps_are_deterministic_and_batch_independent(ctx):
+    pa = _cases()["thermal_couette_fp32"]()
+    pb = _cases()["sod_fp32"]()
+    a1 = ctx.add(pa)
+    a2 = ctx.add(pa)
+    b = ctx.add(pb)
+    ctx.step([a1], 4)
+    ctx.step([a2, b], 4)
+    ctx.sync()
+    s1, s2 = a1.get_state(), a2.get_state()
+    assert np.array_equal(s1.counts, s2.counts)
+    assert np.array_equal(s1.parts, s2.parts)
+    assert np.array_equal(s1.cells, s2.cells)
+    for x in (a1, a2, b):
+        x.free()
+
+
+@pytest.mark.gpu
+def test_capacity_error_is_sticky_and_isolated(ctx):
+    usp = _gpu()
+    small = _cases()["thermal_couette_fp32"]().replace(max_ppc=230)
+    good = _cases()["sod_fp32"]()
+    a = ctx.add(small)
+    b = ctx.add(good)
+    ctx.step([a, b], 3)
+    assert a.status() == -3
+    assert b.status() == 0
+    with pytest.raises(usp.UspError):
+        a.get_state()
+    a.free()
+    b.free()
