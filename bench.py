@@ -1,0 +1,152 @@
+"""Throughput benchmark of the USP-ESBGK particle step on one MI355X.
+
+Workload (the paper's 1-D continuum cases at the sizes of the second
+configuration): a thermal Couette flow and a Sod shock tube, each 1000 cells
+x 500 particles per cell (FP32 state), Kn = 1e-3, dt = 5 mean collision
+times, advanced together in the same kernel launches.  Synthetic inputs
+(seeded Philox initial states); no external data.
+
+A "step" is one full time step (Table 2 steps 2-8) of both instances.
+value = live particles (weighted included) x steps / wall time of the timed
+region, with all state resident in HBM.
+
+Prints one JSON line (see the "roofline" and "cpu_baseline" members).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# algorithmic bytes per particle-step: one read and one write of the particle
+# record (y, cx, cy, cz, w in FP32 = 20 B each way)
+BYTES_PER_PARTICLE_STEP = 40.0
+
+
+def workload():
+    from paper_1808_03801_amd import problems as P
+    tc = P.thermal_couette_1d(Kn=1e-3, ncell=1000, ppc=500, dt_over_tau=5.0, seed=1)
+    sod = P.sod_1d(Kn=1e-3, ncell=1000, mean_ppc=500, dt_over_tau=5.0, seed=2)
+    return [tc, sod]
+
+
+def cpu_baseline(steps=8):
+    """the CPU oracle (single thread, as it stands) on the same two problems
+    for a few steps from their initial state"""
+    from oracle import oracle as O
+    pbs = workload()
+    os_ = [O.Oracle(pb) for pb in pbs]
+    n0 = sum(o.num_particles() for o in os_)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for o in os_:
+            o.step(1)
+    dt = time.perf_counter() - t0
+    n1 = sum(o.num_particles() for o in os_)
+    return dict(value=0.5 * (n0 + n1) * steps / dt, unit="particle-updates/s", cores=1,
+                kind="oracle",
+                sample=f"{steps} steps of both instances from their initial state "
+                       f"({n0}-{n1} live particles), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--chunk", type=int, default=20, help="steps per library call")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--block", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the design notes for how the step would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1808_03801_amd import usp
+
+    pbs = workload()
+    ctx = usp.Context(0)
+    ctx.set_block(args.block)
+    inst = [ctx.add(pb) for pb in pbs]
+
+    def run(n):
+        left = n
+        while left > 0:
+            k = min(args.chunk, left)
+            ctx.step(inst, k)
+            left -= k
+
+    run(args.warmup)
+    ctx.sync()
+    n_before = sum(i.num_particles() for i in inst)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.sync()
+    n_after = sum(i.num_particles() for i in inst)
+    n_live = 0.5 * (n_before + n_after)
+    value = n_live * args.steps / wall
+
+    # fused-kernel time from HIP events on the library's stream
+    ctx.set_timing(True)
+    run(min(args.steps, 100))
+    ms, launches = ctx.timing()
+    ctx.set_timing(False)
+    ctx.sync()
+    n_roof = sum(i.num_particles() for i in inst)
+    avg_ms = ms / max(launches, 1)
+    bytes_per_launch = n_roof * BYTES_PER_PARTICLE_STEP
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+
+    line = {
+        "metric": "particle-updates/s",
+        "value": value,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "thermal Couette + Sod tube (1-D), 1000 cells x 500 particles/cell "
+                        "each, Kn=1e-3, dt=5 tau_c, FP32 particles, FP64 cell moments, "
+                        "both instances batched per launch",
+            "cells": sum(pb.ncell for pb in pbs),
+            "live_particles": int(n_live),
+            "steps_per_call": args.chunk,
+            "block": args.block,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "cell_kernel (fused relax + add + advect + bin)",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": None,
+            "avg_launch_ms": avg_ms,
+            "bytes_per_launch": bytes_per_launch,
+        },
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    for i in inst:
+        i.free()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -170,6 +170,13 @@ usp_status usp_get_diag(usp_ctx* ctx, int id, double* out);
  * default 256).  Applies to later usp_step calls. */
 usp_status usp_set_block(usp_ctx* ctx, int threads);
 
+/* Kernel timing (benchmarking): while on, every launch of the fused cell
+ * kernel is bracketed by two HIP events on the context's stream.
+ * usp_get_timing synchronises and returns the summed event time of those
+ * launches (ms) and their number since timing was switched on. */
+usp_status usp_set_timing(usp_ctx* ctx, int on);
+usp_status usp_get_timing(usp_ctx* ctx, double* ms, long long* launches);
+
 /* Philox4x32-10 evaluated on the device for n counters (ctr [n][4], out
  * [n][4], host arrays) with key (k0, k1); for checking the generator. */
 usp_status usp_philox(usp_ctx* ctx, const uint32_t* ctr, uint32_t k0, uint32_t k1, int n,

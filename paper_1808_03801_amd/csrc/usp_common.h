@@ -10,6 +10,7 @@ constexpr int NMOM = 13;   // centred moments / raw sums per cell
 constexpr int NDIAG = 32;  // per-cell diagnostic record
 constexpr int MAX_BINS = 256;
 constexpr int MAX_PPC = 2048;
+constexpr int FAR_LDS = 128;  // far arrivals one cell can take per step
 
 // control words of an instance (device memory)
 enum { CTL_CUR = 0, CTL_STEP = 1, CTL_NSAMP = 2, CTL_ERR = 3, CTL_N = 4 };
@@ -74,6 +75,12 @@ struct InstDev {
     int* cnt;           // [ncell] particles of f^n per cell
     int* ctl;           // [CTL_N]
     double* diag;       // [ncell][NDIAG] or null
+    // particles displaced beyond the window: per buffer a list of
+    // (destination cell, source offset key, slot) + the particle, and a count
+    int far_cap;
+    int* far_n;         // [2]
+    uint32_t* far_meta[2];  // [far_cap][3]
+    void* far_pc[2][6];
 };
 
 struct Batch {
@@ -99,7 +106,9 @@ inline size_t lds_bytes(int cap, int real_bytes, int dim, int nb, int nthreads)
     b += 256 * 4;                               // histogram
     b += (size_t)((cap + 63) / 64) * nb * 2;    // tile counts
     b = (b + 15) & ~(size_t)15;
-    b += (size_t)(nb + 1) * 4 * 3;              // runs / bin offsets
+    b += (size_t)(nb + 1) * 4 * 4;              // runs / bin offsets
+    b = (b + 15) & ~(size_t)15;
+    b += (size_t)FAR_LDS * (8 + 4 + 4 + 4) + 16;  // far arrivals
     b = (b + 15) & ~(size_t)15;
     b += 64 * 8;                                // scalars
     return b;

@@ -30,7 +30,13 @@ struct Lds {
     uint16_t* tiles;
     uint32_t* run_pre;
     uint32_t* run_src;
+    uint32_t* run_dst;
     uint32_t* boff;
+    uint64_t* fkey;
+    uint32_t* fent;
+    uint32_t* fpos;
+    uint32_t* fib;
+    uint32_t* fcount;
     double* sc;
 };
 
@@ -60,13 +66,22 @@ __device__ __forceinline__ Lds<real> carve(unsigned char* sm, int cap, int nb, i
     o = (o + 15) & ~(size_t)15;
     L.run_pre = (uint32_t*)take((size_t)(nb + 1) * 4);
     L.run_src = (uint32_t*)take((size_t)(nb + 1) * 4);
+    L.run_dst = (uint32_t*)take((size_t)(nb + 1) * 4);
     L.boff = (uint32_t*)take((size_t)(nb + 1) * 4);
+    o = (o + 15) & ~(size_t)15;
+    L.fkey = (uint64_t*)take((size_t)FAR_LDS * 8);
+    L.fent = (uint32_t*)take((size_t)FAR_LDS * 4);
+    L.fpos = (uint32_t*)take((size_t)FAR_LDS * 4);
+    L.fib = (uint32_t*)take((size_t)FAR_LDS * 4);
+    L.fcount = (uint32_t*)take(16);
     o = (o + 15) & ~(size_t)15;
     L.sc = (double*)take(64 * 8);
     return L;
 }
 
 __device__ __forceinline__ int wrap(int i, int n) { return ((i % n) + n) % n; }
+
+constexpr int FAR_BIN = 0xFFFF;
 
 __device__ __forceinline__ int min_image(int d, int n, bool periodic)
 {
@@ -566,7 +581,54 @@ __device__ void process_cell(const InstDev& I, int c, int mode, int cap_lds, uns
         }
         __syncthreads();
     }
-    int n0 = (int)L.run_pre[nb];
+    // far arrivals: particles that left their source cell by more than the
+    // window; merged by their (source offset, slot) key
+    const int nfar_all = I.far_n[cur];
+    int nfc = 0;
+    if (nfar_all > 0) {
+        if (tid == 0) L.fcount[0] = 0u;
+        __syncthreads();
+        const uint32_t* fm = I.far_meta[cur];
+        for (int e = tid; e < nfar_all && e < I.far_cap; e += nt)
+            if ((int)fm[3 * e] == c) {
+                const uint32_t k = atomicAdd(&L.fcount[0], 1u);
+                if (k < (uint32_t)FAR_LDS) {
+                    L.fkey[k] = ((uint64_t)fm[3 * e + 1] << 32) | (uint64_t)fm[3 * e + 2];
+                    L.fent[k] = (uint32_t)e;
+                }
+            }
+        __syncthreads();
+        nfc = (int)L.fcount[0];
+        if (nfc > FAR_LDS) {
+            errbits |= ERR_WINDOW;
+            nfc = FAR_LDS;
+        }
+        // rank among the far arrivals and insertion bin among the window bins
+        for (int k = tid; k < nfc; k += nt) {
+            const uint64_t key = L.fkey[k];
+            uint32_t r = 0;
+            for (int j = 0; j < nfc; ++j) r += L.fkey[j] < key ? 1u : 0u;
+            const int oy = (int)((key >> 48) & 0xFFFF) - 32768;
+            const int ox = (int)((key >> 32) & 0xFFFF) - 32768;
+            int ib;
+            if (oy < -I.Ky) ib = 0;
+            else if (oy > I.Ky) ib = nb;
+            else if (ox < -I.Kx) ib = (oy + I.Ky) * I.nbx;
+            else ib = (oy + I.Ky + 1) * I.nbx;
+            L.fpos[k] = L.run_pre[ib] + r;
+            L.fib[k] = (uint32_t)ib;
+        }
+        __syncthreads();
+    }
+    // first destination slot of every window bin
+    for (int b = tid; b < nb; b += nt) {
+        uint32_t sh = 0;
+        for (int k = 0; k < nfc; ++k) sh += (int)L.fib[k] <= b ? 1u : 0u;
+        L.run_dst[b] = L.run_pre[b] + sh;
+    }
+    __syncthreads();
+    const int nwin = (int)L.run_pre[nb];
+    int n0 = nwin + nfc;
     if (n0 > I.max_ppc) {
         errbits |= ERR_CAPACITY;
         n0 = I.max_ppc;
@@ -574,20 +636,38 @@ __device__ void process_cell(const InstDev& I, int c, int mode, int cap_lds, uns
     {
         const real* in[6];
         for (int k = 0; k < 6; ++k) in[k] = (const real*)I.pc[cur][k];
-        for (int j = tid; j < n0; j += nt) {
+        for (int j = tid; j < nwin; j += nt) {
             int lo = 0, hi = nb - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (L.run_pre[mid] <= (uint32_t)j) lo = mid;
                 else hi = mid - 1;
             }
-            const size_t src = (size_t)L.run_src[lo] + (size_t)(j - (int)L.run_pre[lo]);
-            if (DIM == 2) L.p[0][j] = in[0][src];
-            L.p[1][j] = in[1][src];
-            L.v[0][j] = in[2][src];
-            L.v[1][j] = in[3][src];
-            L.v[2][j] = in[4][src];
-            L.w[j] = in[5][src];
+            const uint32_t off = (uint32_t)j - L.run_pre[lo];
+            const size_t src = (size_t)L.run_src[lo] + off;
+            const int dst = (int)(L.run_dst[lo] + off);
+            if (dst >= n0) continue;
+            if (DIM == 2) L.p[0][dst] = in[0][src];
+            L.p[1][dst] = in[1][src];
+            L.v[0][dst] = in[2][src];
+            L.v[1][dst] = in[3][src];
+            L.v[2][dst] = in[4][src];
+            L.w[dst] = in[5][src];
+        }
+        if (nfc > 0) {
+            const real* fin[6];
+            for (int k = 0; k < 6; ++k) fin[k] = (const real*)I.far_pc[cur][k];
+            for (int k = tid; k < nfc; k += nt) {
+                const size_t src = L.fent[k];
+                const int dst = (int)L.fpos[k];
+                if (dst >= n0) continue;
+                if (DIM == 2) L.p[0][dst] = fin[0][src];
+                L.p[1][dst] = fin[1][src];
+                L.v[0][dst] = fin[2][src];
+                L.v[1][dst] = fin[3][src];
+                L.v[2][dst] = fin[4][src];
+                L.w[dst] = fin[5][src];
+            }
         }
         __syncthreads();
     }
@@ -598,7 +678,9 @@ __device__ void process_cell(const InstDev& I, int c, int mode, int cap_lds, uns
 
     if (mode & MODE_RELAX) {
         if (dg && tid == 0) {
-            for (int k = 0; k < NDIAG; ++k) dg[k] = 0.0;
+            // the step-2 fields were written by the preceding move phase
+            for (int k = 0; k < NDIAG; ++k)
+                if (k != D_N2 && k != D_CLAMP && k != D_MARG_CNT2) dg[k] = 0.0;
             dg[D_NIN] = n0;
         }
         // Eq. 33: moments of f-tilde^*; totals that conservation restores
@@ -880,8 +962,23 @@ __device__ void process_cell(const InstDev& I, int c, int mode, int cap_lds, uns
             const int ox = DIM == 2 ? min_image(ix - dx_, I.nx, per_x) : 0;
             int b;
             if (oy < -I.Ky || oy > I.Ky || ox < -I.Kx || ox > I.Kx) {
-                errbits |= ERR_WINDOW;
-                b = I.Ky * I.nbx + I.Kx;
+                b = FAR_BIN;
+                const int e = atomicAdd(&I.far_n[1 - cur], 1);
+                if (e < I.far_cap) {
+                    uint32_t* fm = I.far_meta[1 - cur] + 3 * (size_t)e;
+                    fm[0] = (uint32_t)d;
+                    fm[1] = ((uint32_t)(oy + 32768) << 16) | (uint32_t)(ox + 32768);
+                    fm[2] = (uint32_t)i;
+                    real* const* fo = (real* const*)I.far_pc[1 - cur];
+                    if (DIM == 2) fo[0][e] = px;
+                    fo[1][e] = py;
+                    fo[2][e] = c0;
+                    fo[3][e] = c1;
+                    fo[4][e] = c2;
+                    fo[5][e] = L.w[i];
+                } else {
+                    errbits |= ERR_WINDOW;
+                }
             } else {
                 b = (oy + I.Ky) * I.nbx + (ox + I.Kx);
             }
@@ -897,11 +994,11 @@ __device__ void process_cell(const InstDev& I, int c, int mode, int cap_lds, uns
             const bool act = i < nmv;
             const int b = act ? (int)L.bin[i] : -1;
             const int tile = i >> 6;
-            uint64_t rem = __ballot(act);
+            uint64_t rem = __ballot(act && b != FAR_BIN);
             while (rem) {
                 const int leader = __ffsll((unsigned long long)rem) - 1;
                 const int bv = __shfl(b, leader, 64);
-                const uint64_t mm = __ballot(act && b == bv);
+                const uint64_t mm = __ballot(act && b == bv && b != FAR_BIN);
                 if (lane == leader) L.tiles[tile * nb + bv] = (uint16_t)__popcll(mm);
                 if (act && b == bv) L.slot[i] = (uint16_t)__popcll(mm & lanemask_lt(lane));
                 rem &= ~mm;
@@ -947,11 +1044,13 @@ __device__ void process_cell(const InstDev& I, int c, int mode, int cap_lds, uns
         }
         __syncthreads();
         for (int i = tid; i < nmv; i += nt) {
+            if (L.bin[i] == FAR_BIN) continue;
             const uint32_t pos = (uint32_t)L.tiles[(i >> 6) * nb + L.bin[i]] + L.slot[i];
             L.key[pos] = (uint32_t)i;
         }
         __syncthreads();
-        for (int p = tid; p < nmv; p += nt) {
+        const int nwrite = (int)L.boff[nb];
+        for (int p = tid; p < nwrite; p += nt) {
             const int i = (int)L.key[p];
             if (DIM == 2) out[0][rbase + p] = L.p[0][i];
             out[1][rbase + p] = L.p[1][i];
@@ -1125,7 +1224,9 @@ __global__ void ctl_kernel(Batch B, int relaxed)
     if (i >= B.ninst) return;
     int* ctl = B.inst[i].ctl;
     if (ctl[CTL_ERR] != 0) return;
-    ctl[CTL_CUR] = 1 - ctl[CTL_CUR];
+    const int oc = ctl[CTL_CUR];
+    ctl[CTL_CUR] = 1 - oc;
+    B.inst[i].far_n[oc] = 0;
     if (relaxed) {
         if (ctl[CTL_STEP] >= B.inst[i].avg_start) ctl[CTL_NSAMP] += 1;
         ctl[CTL_STEP] += 1;

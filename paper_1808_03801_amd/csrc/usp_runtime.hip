@@ -55,6 +55,9 @@ struct usp_ctx {
     std::string err;
     int block = 256;
     size_t allocated = 0;
+    // kernel timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     // batch descriptor cache
     std::vector<int> last_ids;
     InstDev* bd = nullptr;
@@ -173,6 +176,8 @@ size_t footprint_of(const usp_problem* pb, const usp_numerics* nm, int nb)
     b += 2 * ncell * (size_t)(nb + 1) * 4;              // bin tables
     b += 4 * NMOM * ncell * 8;                          // moments
     b += 2 * ncell * 8 + ncell * 4 + 64;                // P_ne, counts, ctl
+    const size_t far_cap = std::max((size_t)4096, ncell * 8);
+    b += 2 * far_cap * (12 + (size_t)(pb->dim + 4) * rb);  // far-mover lists
     return b;
 }
 
@@ -201,8 +206,18 @@ usp_status launch_cell(usp_ctx* ctx, const Batch& B, int prec, int dim, int max_
         auto kern = cell_kernel<real, D>;
         HIPCHK(ctx, hipFuncSetAttribute((const void*)kern,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (ctx->timing) {
+            HIPCHK(ctx, hipEventCreate(&e0));
+            HIPCHK(ctx, hipEventCreate(&e1));
+            HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
+        }
         hipLaunchKernelGGL(kern, dim3(B.ncells), dim3(nthreads), lds, ctx->stream, B);
         HIPCHK(ctx, hipGetLastError());
+        if (ctx->timing) {
+            HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
+            ctx->events.emplace_back(e0, e1);
+        }
         return USP_OK;
     });
 }
@@ -394,6 +409,21 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
         h.tab[b] = (uint32_t*)A(ncell * (h.nb + 1) * 4);
         ok = ok && h.tab[b];
     }
+    h.far_cap = (int)std::max((size_t)4096, ncell * 8);
+    h.far_n = (int*)A(2 * sizeof(int));
+    ok = ok && h.far_n;
+    for (int b = 0; b < 2; ++b) {
+        h.far_meta[b] = (uint32_t*)A((size_t)h.far_cap * 12);
+        ok = ok && h.far_meta[b];
+        for (int k = 0; k < 6; ++k) {
+            if (k == 0 && h.dim == 1) {
+                h.far_pc[b][k] = nullptr;
+                continue;
+            }
+            h.far_pc[b][k] = A((size_t)h.far_cap * rb);
+            ok = ok && h.far_pc[b][k];
+        }
+    }
     h.mom = (double*)A(NMOM * ncell * 8);
     h.raw = (double*)A(NMOM * ncell * 8);
     h.avg = (double*)A(NMOM * ncell * 8);
@@ -415,6 +445,7 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
     HIPCHK(ctx, hipMemsetAsync(h.avg, 0, NMOM * ncell * 8, ctx->stream));
     HIPCHK(ctx, hipMemsetAsync(h.avgs, 0, NMOM * ncell * 8, ctx->stream));
     HIPCHK(ctx, hipMemsetAsync(h.ctl, 0, CTL_N * 4, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(h.far_n, 0, 2 * sizeof(int), ctx->stream));
     int base[2] = {0, h.ncell};
     HIPCHK(ctx, hipMemcpyAsync(in->dbase, base, sizeof(base), hipMemcpyHostToDevice, ctx->stream));
     if ((s = upload_desc(ctx, in))) return s;
@@ -681,6 +712,7 @@ usp_status usp_set_state(usp_ctx* ctx, int id, const int* counts, const double* 
     HIPCHK(ctx, hipMemcpy(h.cnt, counts, ncell * 4, hipMemcpyHostToDevice));
     int nctl[CTL_N] = {cur, step, cells ? n_samples : 0, 0};
     HIPCHK(ctx, hipMemcpy(h.ctl, nctl, sizeof(nctl), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemset(h.far_n, 0, 2 * sizeof(int)));
     if (cells) {
         std::vector<double> a(NMOM * ncell);
         double* arrs[4] = {h.mom, h.raw, h.avg, h.avgs};
@@ -744,6 +776,34 @@ usp_status usp_get_diag(usp_ctx* ctx, int id, double* out)
     HIPCHK(ctx, hipMemcpyAsync(out, in->h.diag, (size_t)in->h.ncell * NDIAG * 8,
                                hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return USP_OK;
+}
+
+usp_status usp_set_timing(usp_ctx* ctx, int on)
+{
+    if (!ctx) return USP_EINVAL;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto& e : ctx->events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    ctx->events.clear();
+    ctx->timing = on != 0;
+    return USP_OK;
+}
+
+usp_status usp_get_timing(usp_ctx* ctx, double* ms, long long* launches)
+{
+    if (!ctx || !ms || !launches) return USP_EINVAL;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    double t = 0.0;
+    for (auto& e : ctx->events) {
+        float f = 0.0f;
+        HIPCHK(ctx, hipEventElapsedTime(&f, e.first, e.second));
+        t += f;
+    }
+    *ms = t;
+    *launches = (long long)ctx->events.size();
     return USP_OK;
 }
 

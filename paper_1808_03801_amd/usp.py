@@ -97,6 +97,8 @@ def lib():
             "usp_get_diag": (C.c_int, [vp, C.c_int, dp]),
             "usp_set_block": (C.c_int, [vp, C.c_int]),
             "usp_philox": (C.c_int, [vp, u32p, C.c_uint32, C.c_uint32, C.c_int, u32p]),
+            "usp_set_timing": (C.c_int, [vp, C.c_int]),
+            "usp_get_timing": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -111,7 +113,8 @@ def exported_symbols():
     return ["usp_create", "usp_destroy", "usp_last_error", "usp_footprint", "usp_instance_init",
             "usp_instance_free", "usp_step", "usp_sync", "usp_instance_status", "usp_num_cells",
             "usp_num_particles", "usp_get_state", "usp_set_state", "usp_get_fields",
-            "usp_set_diag", "usp_get_diag", "usp_set_block", "usp_philox"]
+            "usp_set_diag", "usp_get_diag", "usp_set_block", "usp_philox", "usp_set_timing",
+            "usp_get_timing"]
 
 
 def _dp(a):
@@ -243,6 +246,15 @@ class Context:
 
     def set_block(self, threads: int):
         _check(self.h, lib().usp_set_block(self.h, int(threads)))
+
+    def set_timing(self, on: bool):
+        _check(self.h, lib().usp_set_timing(self.h, int(on)))
+
+    def timing(self):
+        """(summed fused-kernel event time in ms, number of launches)"""
+        ms, n = C.c_double(), C.c_longlong()
+        _check(self.h, lib().usp_get_timing(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def philox(self, ctr, key):
         ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)

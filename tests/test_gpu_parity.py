@@ -59,7 +59,16 @@ def _cases():
                                                        precision=64, seed=8),
         "poiseuille_fp32": lambda: P.poiseuille_1d(Kn=0.01, dpdx=1.6e8, ncell=50, ppc=200,
                                                    dt_over_tau=2.0, seed=9),
+        # sort windows narrower than the fastest particles: the far-mover path
+        "sod_fp32_far": lambda: _window(P.sod_1d(ncell=150, mean_ppc=200, seed=10), 2),
+        "cavity_fp32_far": lambda: _window(P.cavity_2d(Kn=0.01, n=16, ppc=80, seed=11), 1),
+        "box_fp64_far": lambda: _window(P.homogeneous_box(ncell=15, ppc=300, nu_dt=2.0, pne=0.7,
+                                                          precision=64, seed=12), 1),
     }
+
+
+def _window(pb, k):
+    return pb.replace(meta={**pb.meta, "window": k})
 
 
 @pytest.mark.gpu
