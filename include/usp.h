@@ -161,13 +161,18 @@ usp_status usp_set_state(usp_ctx* ctx, int id, const int* counts, const double* 
  * S0, rho, u[3], T, p, sigma[6] (xx yy zz xy xz yz), q[3], P_ne, count. */
 usp_status usp_get_fields(usp_ctx* ctx, int id, int which, double* out);
 
-/* Per-cell diagnostics of the last step, [ncell][32] (enable first with
- * usp_set_diag; costs one record write per cell per step). */
+/* Per-cell diagnostics, [ncell][48] (enable first with usp_set_diag; costs a
+ * few record writes per cell per step).  Slots 0..31 describe the last step
+ * (same meaning as the oracle's record); slots 32..46 accumulate the shader
+ * cycles spent in each phase of the cell kernel (gather, moments, step 4,
+ * selection, rank selection, resampling, step 7, conservation, compaction,
+ * step-8 moments, step 2, advection, bin counts, bin offsets, writes). */
 usp_status usp_set_diag(usp_ctx* ctx, int id, int on);
 usp_status usp_get_diag(usp_ctx* ctx, int id, double* out);
 
-/* Launch shape: threads per cell workgroup (64..256, multiple of 64; 0 =
- * default 256).  Applies to later usp_step calls. */
+/* Launch shape: threads per cell workgroup.  The cell kernel keeps a cell's
+ * particles in the registers of 256 threads, so 256 (or 0 for the default)
+ * is the only accepted value; others return USP_EINVAL. */
 usp_status usp_set_block(usp_ctx* ctx, int threads);
 
 /* Kernel timing (benchmarking): while on, every launch of the fused cell

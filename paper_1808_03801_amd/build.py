@@ -8,13 +8,16 @@ LIB = os.path.join(HERE, "libusp.so")
 ARCH = os.environ.get("USP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+         # no implicit FMA contraction: results must not depend on which
+         # kernel instantiation (particles per thread) ran a cell
+         "-ffp-contract=off",
          # packed FP32 instructions stay off (see the design notes)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, f) for f in ("usp_kernels.hip", "usp_runtime.hip")]
+    srcs = [os.path.join(CSRC, f) for f in ("usp_cell.hip", "usp_kernels.hip", "usp_runtime.hip")]
     cmd = ["hipcc", *FLAGS, *srcs, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -1,0 +1,1155 @@
+// gfx950 cell kernel of the USP-ESBGK time step (arXiv 1808.03801, Table 2).
+//
+// One 256-thread workgroup owns one cell at a time.  The cell's particles
+// live in registers: particle j of the cell is held by thread j % 256 in
+// register slot j / 256 (PPT slots per thread, fully unrolled), so every
+// per-particle phase runs without LDS traffic and with PPT independent
+// instruction streams per thread.  LDS holds only small tables: the gather
+// map, bin tile counts, histograms and reduction scratch.
+//
+// Phases for one cell (mode bits select them):
+//   gather    read the cell's arrivals from the neighbours' bins in canonical
+//             order (source offset, then source slot), far movers merged in;
+//   relax     Eq. 33 moments, step 4 (added particles for f^*), step 5
+//             (Bernoulli selection, keep int(sum W) with the smallest keys),
+//             step 6 (f_G(t) resampling), step 7 (added particles), the
+//             conservation correction, step 8 moments and Eq. 34 averages;
+//   move      step 2 of the next time level, step 3 (advect, walls), and the
+//             write-out grouped by destination offset with a bin table;
+//   stay      (no move) write the cell's particles back in slot order.
+//
+// Particles removed in step 5 are not moved out of their registers: their
+// fate marks them dead, and the logical slot of each survivor comes from a
+// scan.  Physical order is monotone in logical order, so stable ranks taken
+// over physical positions equal those over logical slots.
+#include "usp_device.h"
+
+namespace usp {
+
+constexpr int NT = 256;
+constexpr int NW = NT / 64;
+constexpr int FAR_BIN = 0xFFFF;
+constexpr uint32_t FARBIT = 0x80000000u;
+
+// fate codes
+enum { FT_KEEP = 0, FT_REASSIGN = 1, FT_DELETE = 2, FT_SEL = 3, FT_EMPTY = 4 };
+
+struct Lds {
+    uint32_t* srcmap;  // [cap] source index of each gathered position
+    uint16_t* tiles;   // [cap / 64][nb]
+    uint32_t* hist;    // [256]
+    uint32_t* wtot;    // [64] per-wave scan totals
+    double* red;       // [NW][24]
+    uint32_t* run_pre;
+    uint32_t* run_src;
+    uint32_t* run_dst;
+    uint32_t* boff;
+    uint64_t* fkey;
+    uint32_t* fent;
+    uint32_t* fpos;
+    uint32_t* fib;
+    uint32_t* fcount;
+    double* sc;
+    CellF* f;      // cell scalars shared by the workgroup
+    double* mom;   // [0..12] centred, [13..25] raw, [26] energy, [27..29] momentum
+};
+
+static_assert(sizeof(CellF) <= 256, "cell scalars must fit their LDS slot");
+
+__device__ __forceinline__ Lds carve(unsigned char* sm, int cap, int nb)
+{
+    Lds L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* q = sm + o;
+        o += (bytes + 15) & ~(size_t)15;
+        return q;
+    };
+    L.srcmap = (uint32_t*)take((size_t)cap * 4);
+    L.tiles = (uint16_t*)take((size_t)(cap / 64) * nb * 2);
+    L.hist = (uint32_t*)take(256 * 4);
+    L.wtot = (uint32_t*)take(64 * 4);
+    L.red = (double*)take((size_t)NW * 24 * 8);
+    L.run_pre = (uint32_t*)take((size_t)(nb + 1) * 4);
+    L.run_src = (uint32_t*)take((size_t)(nb + 1) * 4);
+    L.run_dst = (uint32_t*)take((size_t)(nb + 1) * 4);
+    L.boff = (uint32_t*)take((size_t)(nb + 1) * 4);
+    L.fkey = (uint64_t*)take((size_t)FAR_LDS * 8);
+    L.fent = (uint32_t*)take((size_t)FAR_LDS * 4);
+    L.fpos = (uint32_t*)take((size_t)FAR_LDS * 4);
+    L.fib = (uint32_t*)take((size_t)FAR_LDS * 4);
+    L.fcount = (uint32_t*)take(16);
+    L.sc = (double*)take(64 * 8);
+    L.f = (CellF*)take(sizeof(CellF));
+    L.mom = (double*)take(32 * 8);
+    return L;
+}
+
+template <int K>
+__device__ __forceinline__ void bsum(double (&v)[K], double* red, int tid)
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    const int lane = tid & 63, wave = tid >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += red[w * K + k];
+        v[k] = s;
+    }
+}
+
+__device__ __forceinline__ double bmin(double v, double* red, int tid)
+{
+    v = wave_min(v);
+    const int lane = tid & 63, wave = tid >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double m = red[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) m = fmin(m, red[w]);
+    return m;
+}
+
+// exclusive prefix of flag over physical positions j = k * NT + tid
+template <int PPT>
+__device__ __forceinline__ int phys_scan(const bool (&flag)[PPT], int (&pre)[PPT], uint32_t* wtot,
+                                         int tid)
+{
+    const int lane = tid & 63, wave = tid >> 6;
+    int wpre[PPT];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const uint64_t m = __ballot(flag[k]);
+        wpre[k] = __popcll(m & lanemask_lt(lane));
+        if (lane == 0) wtot[k * NW + wave] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    int base = 0;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        int off = base, tot = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int t = (int)wtot[k * NW + w];
+            if (w < wave) off += t;
+            tot += t;
+        }
+        pre[k] = off + wpre[k];
+        base += tot;
+    }
+    return base;
+}
+
+// exclusive scan of up to 256 counters in place by the first wave; a[n] = total
+__device__ __forceinline__ void wave0_scan(uint32_t* a, int n, int tid)
+{
+    if (tid < 64) {
+        uint32_t loc[4], s = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int b = 4 * tid + q;
+            loc[q] = b < n ? a[b] : 0u;
+            s += loc[q];
+        }
+        uint32_t incl = s;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o, 64);
+            if (tid >= o) incl += t;
+        }
+        uint32_t run = incl - s;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int b = 4 * tid + q;
+            if (b < n) a[b] = run;
+            run += loc[q];
+        }
+        if (tid == 63) a[n] = incl;
+    }
+}
+
+template <typename real, int DIM, int PPT>
+struct Parts {
+    real x[DIM == 2 ? PPT : 1];
+    real y[PPT], c0[PPT], c1[PPT], c2[PPT], w[PPT];
+    uint32_t key[PPT];  // rank key (relax), bin / output position (move)
+    uint32_t st[PPT];   // fate | logical slot << 8
+};
+
+template <typename real, int DIM, int PPT>
+__device__ __forceinline__ int fate(const Parts<real, DIM, PPT>& P, int k)
+{
+    return (int)(P.st[k] & 0xFFu);
+}
+
+// ---------------------------------------------------------------------------
+// moments of the live particles (fate keep or reassigned): centred (two
+// passes) and raw sums; E = sum w |c|^2 / 2.  Every thread gets the results.
+// ---------------------------------------------------------------------------
+template <typename real, int DIM, int PPT>
+__device__ void moments_r(const Parts<real, DIM, PPT>& P, const Lds& L, int tid, double* cen,
+                          double* raw, double* E)
+{
+    double a[14];
+#pragma unroll
+    for (int q = 0; q < 14; ++q) a[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (fate(P, k) <= FT_REASSIGN) {
+            const double w = (double)P.w[k];
+            const double c0 = (double)P.c0[k], c1 = (double)P.c1[k], c2 = (double)P.c2[k];
+            const double cc = c0 * c0 + c1 * c1 + c2 * c2;
+            a[0] += w;
+            a[1] += w * c0;
+            a[2] += w * c1;
+            a[3] += w * c2;
+            a[4] += 0.5 * w * cc;
+            a[5] += w * c0 * c0;
+            a[6] += w * c1 * c1;
+            a[7] += w * c2 * c2;
+            a[8] += w * c0 * c1;
+            a[9] += w * c0 * c2;
+            a[10] += w * c1 * c2;
+            a[11] += w * cc * c0;
+            a[12] += w * cc * c1;
+            a[13] += w * cc * c2;
+        }
+    }
+    bsum(a, L.red, tid);
+    const double s0 = a[0];
+    double U[3] = {0.0, 0.0, 0.0};
+    if (s0 != 0.0)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) U[q] = a[1 + q] / s0;
+    double b[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) b[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (fate(P, k) <= FT_REASSIGN) {
+            const double w = (double)P.w[k];
+            const double C0 = (double)P.c0[k] - U[0], C1 = (double)P.c1[k] - U[1];
+            const double C2 = (double)P.c2[k] - U[2];
+            const double CC = C0 * C0 + C1 * C1 + C2 * C2;
+            b[0] += w * C0 * C0;
+            b[1] += w * C1 * C1;
+            b[2] += w * C2 * C2;
+            b[3] += w * C0 * C1;
+            b[4] += w * C0 * C2;
+            b[5] += w * C1 * C2;
+            b[6] += w * CC * C0;
+            b[7] += w * CC * C1;
+            b[8] += w * CC * C2;
+        }
+    }
+    bsum(b, L.red, tid);
+    cen[0] = s0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) cen[1 + q] = U[q];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) cen[4 + q] = b[q];
+    *E = a[4];
+    raw[0] = a[0];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) raw[1 + q] = a[1 + q];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) raw[4 + q] = a[5 + q];
+}
+
+// ---------------------------------------------------------------------------
+// Added particles of batch 2, 4 or 7 (Eq. 25-27, Table 2) at physical
+// positions [a, a + n) with logical slots [ls, ls + n).  Sampling in double
+// precision, stored once rounded.  Optional zero-moment projection.
+// ---------------------------------------------------------------------------
+template <typename real, int DIM, int PPT>
+__device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L, int batch,
+                       int cell, int ix, int iy, uint32_t step, const CellF& f, double pne, int a,
+                       int ls, int tid, uint32_t* errbits, double* marg)
+{
+    if (!f.valid || !(pne > 0.0) || !(f.x > 0.0)) return 0;
+    const double m1 = f.x < 1.0 ? f.x : 1.0;
+    const double v = f.S0 * m1 / I.r_p;
+    uint32_t r[4];
+    draw(I, step, PUR_SPAWN_CNT, (uint32_t)batch, (uint32_t)cell, 0u, r);
+    const double u = uni_d(r[0], I.prec);
+    const double fl = floor(v);
+    int na = (int)fl + (u < v - fl ? 1 : 0);
+    if (marg) *marg = fmin(*marg, fabs(u - (v - fl)));
+    if (ls + na > I.max_ppc || a + na > PPT * NT) {
+        *errbits |= ERR_CAPACITY;
+        const int room_log = I.max_ppc - ls, room_phys = PPT * NT - a;
+        na = room_log < room_phys ? room_log : room_phys;
+        if (na < 0) na = 0;
+    }
+    double cw = I.r_p * f.nu * pne * I.dt / 2.0;
+    if (I.weight_mode == 0) cw /= m1;
+    const double factor = batch == 7 ? -2.0 * (-expm1(-f.x)) / f.x : 1.0;
+    const double sq = sqrt(f.theta);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int j = k * NT + tid;
+        if (j >= a && j < a + na) {
+            const int q = j - a;
+            uint32_t rr[4];
+            draw(I, step, PUR_SPAWN_POS, (uint32_t)batch, (uint32_t)cell, (uint32_t)q, rr);
+            const double uy = uni_d(rr[0], I.prec), ux = uni_d(rr[1], I.prec);
+            P.y[k] = (real)(I.y0 + ((double)iy + uy) * I.dy);
+            if (DIM == 2) P.x[k] = (real)(I.x0 + ((double)ix + ux) * I.dx);
+            draw(I, step, PUR_SPAWN_VEL, (uint32_t)batch, (uint32_t)cell, (uint32_t)q, rr);
+            double z[3], C[3];
+            normal3_d(rr, I.prec, z);
+            C[0] = sq * z[0];
+            C[1] = sq * z[1];
+            C[2] = sq * z[2];
+            P.c0[k] = (real)(f.U[0] + C[0]);
+            P.c1[k] = (real)(f.U[1] + C[1]);
+            P.c2[k] = (real)(f.U[2] + C[2]);
+            P.w[k] = (real)(-cw * grad_bracket(I.Pr, f, C) * factor);
+            P.st[k] = (uint32_t)FT_KEEP | ((uint32_t)(ls + q) << 8);
+        }
+    }
+    if (I.proj && na >= 5) {
+        double g[20];
+#pragma unroll
+        for (int q = 0; q < 20; ++q) g[q] = 0.0;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int j = k * NT + tid;
+            if (j >= a && j < a + na) {
+                double psi[5];
+                psi5((double)P.c0[k], (double)P.c1[k], (double)P.c2[k], f.U, sq, f.theta, psi);
+                const double w = (double)P.w[k];
+                int q = 0;
+#pragma unroll
+                for (int r1 = 0; r1 < 5; ++r1)
+#pragma unroll
+                    for (int s1 = 0; s1 <= r1; ++s1) g[q++] += psi[r1] * psi[s1];
+#pragma unroll
+                for (int r1 = 0; r1 < 5; ++r1) g[15 + r1] += w * psi[r1];
+            }
+        }
+        bsum(g, L.red, tid);
+        double G[5][5], Lc[5][5];
+        {
+            int q = 0;
+#pragma unroll
+            for (int r1 = 0; r1 < 5; ++r1)
+#pragma unroll
+                for (int s1 = 0; s1 <= r1; ++s1) {
+                    G[r1][s1] = g[q];
+                    G[s1][r1] = g[q];
+                    ++q;
+                }
+        }
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 5; ++jj) Lc[i][jj] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+#pragma unroll
+            for (int jj = 0; jj <= i; ++jj) {
+                double t = G[i][jj];
+#pragma unroll
+                for (int q = 0; q < jj; ++q) t -= Lc[i][q] * Lc[jj][q];
+                if (i == jj) {
+                    ok = ok && (t > 1e-10 * G[0][0]);
+                    Lc[i][i] = sqrt(t > 0.0 ? t : 1.0);
+                } else {
+                    Lc[i][jj] = t / Lc[jj][jj];
+                }
+            }
+        if (ok) {
+            double y[5], lam[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                double t = g[15 + i];
+#pragma unroll
+                for (int q = 0; q < i; ++q) t -= Lc[i][q] * y[q];
+                y[i] = t / Lc[i][i];
+            }
+#pragma unroll
+            for (int i = 4; i >= 0; --i) {
+                double t = y[i];
+#pragma unroll
+                for (int q = i + 1; q < 5; ++q) t -= Lc[q][i] * lam[q];
+                lam[i] = t / Lc[i][i];
+            }
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int j = k * NT + tid;
+                if (j >= a && j < a + na) {
+                    double psi[5];
+                    psi5((double)P.c0[k], (double)P.c1[k], (double)P.c2[k], f.U, sq, f.theta,
+                         psi);
+                    double d = 0.0;
+#pragma unroll
+                    for (int r1 = 0; r1 < 5; ++r1) d += psi[r1] * lam[r1];
+                    P.w[k] = (real)((double)P.w[k] - d);
+                }
+            }
+        }
+    }
+    return na;
+}
+
+// ---------------------------------------------------------------------------
+// f_G(t) velocity of one reassigned particle (Table 2 step 6; Eq. 6c, 29-32).
+// The time-sample uniform is word 2 of the particle's selection draw.
+// ---------------------------------------------------------------------------
+template <typename real>
+__device__ __forceinline__ int resample_one(const InstDev& I, int cell, int slot, uint32_t step,
+                                            const CellF& f, double pne, real& c0, real& c1,
+                                            real& c2)
+{
+    uint32_t r[4];
+    draw(I, step, PUR_SELECT, 0u, (uint32_t)cell, (uint32_t)slot, r);
+    double alpha;
+    if (sizeof(real) == 4) {
+        const float u = uni_f(r[2]);
+        const float x = (float)f.x, nues = (float)(I.Pr * f.nu);
+        const float tf = (float)I.dt + logf(u + (1.0f - u) * expf(-x)) / nues;
+        alpha = (double)((float)pne + (1.0f - (float)pne) * expf(-(float)f.nu * tf));
+    } else {
+        const double u = uni_d(r[2], I.prec);
+        const double t = I.dt + log(u + (1.0 - u) * exp(-f.x)) / (I.Pr * f.nu);
+        alpha = pne + (1.0 - pne) * exp(-f.nu * t);
+    }
+    const double cc = (1.0 - 1.0 / I.Pr) * alpha;
+    const double th = f.theta;
+    const double l00 = th * (1.0 + cc * f.s[0]), l11 = th * (1.0 + cc * f.s[1]);
+    const double l22 = th * (1.0 + cc * f.s[2]);
+    const double l10 = th * cc * f.s[3], l20 = th * cc * f.s[4], l21 = th * cc * f.s[5];
+    const double tiny = 1e-12 * th;
+    double L00 = 0, L10 = 0, L20 = 0, L11 = 0, L21 = 0, L22 = 0;
+    int fb = 0;
+    if (!(l00 > tiny)) fb = 1;
+    if (!fb) {
+        L00 = sqrt(l00);
+        const double iL00 = 1.0 / L00;
+        L10 = l10 * iL00;
+        L20 = l20 * iL00;
+        const double d1 = l11 - L10 * L10;
+        if (!(d1 > tiny)) fb = 1;
+        if (!fb) {
+            L11 = sqrt(d1);
+            L21 = (l21 - L20 * L10) / L11;
+            const double d2 = l22 - L20 * L20 - L21 * L21;
+            if (!(d2 > tiny)) fb = 1;
+            else L22 = sqrt(d2);
+        }
+    }
+    if (fb) {
+        L00 = L11 = L22 = sqrt(th);
+        L10 = L20 = L21 = 0.0;
+    }
+    draw(I, step, PUR_RESAMPLE, 0u, (uint32_t)cell, (uint32_t)slot, r);
+    double z[3];
+    if (sizeof(real) == 4) {
+        float zf[3];
+        normal3_f(r, zf);
+        z[0] = zf[0];
+        z[1] = zf[1];
+        z[2] = zf[2];
+    } else {
+        normal3_d(r, I.prec, z);
+    }
+    c0 = (real)(f.U[0] + L00 * z[0]);
+    c1 = (real)(f.U[1] + L10 * z[0] + L11 * z[1]);
+    c2 = (real)(f.U[2] + L20 * z[0] + L21 * z[1] + L22 * z[2]);
+    return fb;
+}
+
+// k-th smallest (1-based) rank key among the selected particles: 4 passes of
+// an 8-bit LDS histogram, most significant digit first
+template <typename real, int DIM, int PPT>
+__device__ uint32_t kth_key_r(const Parts<real, DIM, PPT>& P, const Lds& L, int kth, int tid)
+{
+    uint32_t prefix = 0;
+    int rem = kth;
+#pragma unroll 1
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        L.hist[tid] = 0u;
+        __syncthreads();
+        const uint32_t hmask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            if (fate(P, k) == FT_SEL && (P.key[k] & hmask) == prefix)
+                atomicAdd(&L.hist[(P.key[k] >> shift) & 255u], 1u);
+        __syncthreads();
+        if (tid < 64) {
+            uint32_t c4[4], s = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c4[q] = L.hist[4 * tid + q];
+                s += c4[q];
+            }
+            uint32_t incl = s;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(incl, o, 64);
+                if (tid >= o) incl += t;
+            }
+            uint32_t run = incl - s;
+            int found = -1;
+            uint32_t before = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (found < 0 && run < (uint32_t)rem && run + c4[q] >= (uint32_t)rem) {
+                    found = 4 * tid + q;
+                    before = run;
+                }
+                run += c4[q];
+            }
+            const uint64_t m = __ballot(found >= 0);
+            const int src = m ? __ffsll((unsigned long long)m) - 1 : 0;
+            const int fb = __builtin_amdgcn_readlane(found, src);
+            const int bb = __builtin_amdgcn_readlane((int)before, src);
+            if (tid == 0) {
+                L.wtot[62] = (uint32_t)fb;
+                L.wtot[63] = (uint32_t)bb;
+            }
+        }
+        __syncthreads();
+        const uint32_t digit = L.wtot[62] & 255u;
+        rem -= (int)L.wtot[63];
+        prefix |= digit << shift;
+        __syncthreads();
+    }
+    return prefix;
+}
+
+template <typename real, int DIM, int PPT>
+__device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char* smem, int tid)
+{
+    const int* ctl = I.ctl;
+    if (ctl[CTL_ERR] != 0) return;
+    const int cur = ctl[CTL_CUR];
+    const uint32_t step = (uint32_t)ctl[CTL_STEP];
+    const int nsamp = ctl[CTL_NSAMP];
+    const int nb = I.nb;
+    constexpr int CAP = PPT * NT;
+    const Lds L = carve(smem, CAP, nb);
+    const int ix = c % I.nx, iy = c / I.nx;
+    const bool per_x = I.face_kind[0] == 2, per_y = I.face_kind[2] == 2;
+    uint32_t errbits = 0;
+    double* dg = I.diag ? I.diag + (size_t)c * NDIAG : nullptr;
+    long long tmark = clock64();
+    auto mark = [&](int k) {
+        if (dg && tid == 0) {
+            const long long t = clock64();
+            dg[NDIAG_STEP + k] += (double)(t - tmark);
+            tmark = t;
+        }
+    };
+    Parts<real, DIM, PPT> P;
+
+    // ---- gather: window bins of the neighbours, then far arrivals
+    {
+        const uint32_t* tin = I.tab[cur];
+        for (int b = tid; b < nb; b += NT) {
+            const int oy = b / I.nbx - I.Ky, ox = b % I.nbx - I.Kx;
+            int sy = iy + oy, sx = ix + ox;
+            bool ok = true;
+            if (per_y) sy = wrap(sy, I.ny);
+            else ok = ok && sy >= 0 && sy < I.ny;
+            if (DIM == 2) {
+                if (per_x) sx = wrap(sx, I.nx);
+                else ok = ok && sx >= 0 && sx < I.nx;
+            } else {
+                sx = 0;
+            }
+            uint32_t len = 0, base = 0;
+            if (ok) {
+                const int s = sy * I.nx + sx;
+                const uint32_t* t = tin + (size_t)s * (nb + 1);
+                const uint32_t a0 = t[b], a1 = t[b + 1];
+                len = a1 - a0;
+                base = (uint32_t)s * (uint32_t)I.cap + a0;
+            }
+            L.run_pre[b] = len;
+            L.run_src[b] = base;
+        }
+        if (tid == 0) L.fcount[0] = 0u;
+        __syncthreads();
+        wave0_scan(L.run_pre, nb, tid);
+        const int nfar_all = I.far_n[cur];
+        if (nfar_all > 0) {
+            const uint32_t* fm = I.far_meta[cur];
+            for (int e = tid; e < nfar_all && e < I.far_cap; e += NT)
+                if ((int)fm[3 * e] == c) {
+                    const uint32_t k = atomicAdd(&L.fcount[0], 1u);
+                    if (k < (uint32_t)FAR_LDS) {
+                        L.fkey[k] = ((uint64_t)fm[3 * e + 1] << 32) | (uint64_t)fm[3 * e + 2];
+                        L.fent[k] = (uint32_t)e;
+                    }
+                }
+        }
+        __syncthreads();
+    }
+    int nfc = (int)L.fcount[0];
+    if (nfc > FAR_LDS) {
+        errbits |= ERR_WINDOW;
+        nfc = FAR_LDS;
+    }
+    if (nfc > 0) {
+        for (int k = tid; k < nfc; k += NT) {
+            const uint64_t key = L.fkey[k];
+            uint32_t r = 0;
+            for (int j = 0; j < nfc; ++j) r += L.fkey[j] < key ? 1u : 0u;
+            const int oy = (int)((key >> 48) & 0xFFFF) - 32768;
+            const int ox = (int)((key >> 32) & 0xFFFF) - 32768;
+            int ib;
+            if (oy < -I.Ky) ib = 0;
+            else if (oy > I.Ky) ib = nb;
+            else if (ox < -I.Kx) ib = (oy + I.Ky) * I.nbx;
+            else ib = (oy + I.Ky + 1) * I.nbx;
+            L.fpos[k] = L.run_pre[ib] + r;
+            L.fib[k] = (uint32_t)ib;
+        }
+        __syncthreads();
+    }
+    for (int b = tid; b < nb; b += NT) {
+        uint32_t sh = 0;
+        for (int k = 0; k < nfc; ++k) sh += (int)L.fib[k] <= b ? 1u : 0u;
+        L.run_dst[b] = L.run_pre[b] + sh;
+    }
+    __syncthreads();
+    const int nwin = (int)L.run_pre[nb];
+    int n0 = nwin + nfc;
+    if (n0 > I.max_ppc || n0 > CAP) {
+        errbits |= ERR_CAPACITY;
+        n0 = I.max_ppc < CAP ? I.max_ppc : CAP;
+    }
+    for (int j = tid; j < nwin; j += NT) {
+        int lo = 0, hi = nb - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L.run_pre[mid] <= (uint32_t)j) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t off = (uint32_t)j - L.run_pre[lo];
+        const uint32_t dst = L.run_dst[lo] + off;
+        if ((int)dst < n0) L.srcmap[dst] = L.run_src[lo] + off;
+    }
+    for (int k = tid; k < nfc; k += NT)
+        if ((int)L.fpos[k] < n0) L.srcmap[L.fpos[k]] = FARBIT | L.fent[k];
+    __syncthreads();
+    {
+        const real* in[6];
+        const real* fin[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            in[q] = (const real*)I.pc[cur][q];
+            fin[q] = (const real*)I.far_pc[cur][q];
+        }
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int j = k * NT + tid;
+            if (j < n0) {
+                const uint32_t s = L.srcmap[j];
+                const real* const* src = (s & FARBIT) ? fin : in;
+                const size_t e = (size_t)(s & ~FARBIT);
+                if (DIM == 2) P.x[k] = src[0][e];
+                P.y[k] = src[1][e];
+                P.c0[k] = src[2][e];
+                P.c1[k] = src[3][e];
+                P.c2[k] = src[4][e];
+                P.w[k] = src[5][e];
+                P.st[k] = (uint32_t)FT_KEEP | ((uint32_t)j << 8);
+            } else {
+                P.st[k] = FT_EMPTY;
+            }
+        }
+    }
+    mark(0);
+
+    int nphys = n0;  // physical positions in use
+    int nlog = n0;   // live particles (logical count)
+    // the workgroup-uniform cell scalars live in LDS: computed by lane 0 of
+    // wave 0, read by everyone (keeps them out of the per-lane registers)
+    CellF& f = *L.f;
+    double* Ms = L.mom;
+
+    if (mode & MODE_RELAX) {
+        if (dg && tid == 0) {
+            for (int k = 0; k < NDIAG_STEP; ++k)
+                if (k != D_N2 && k != D_CLAMP && k != D_MARG_CNT2) dg[k] = 0.0;
+            dg[D_NIN] = n0;
+        }
+        {
+            double cen[NMOM], rawt[NMOM], E0;
+            moments_r(P, L, tid, cen, rawt, &E0);
+            if (tid == 0) {
+                for (int q = 0; q < NMOM; ++q) Ms[q] = cen[q];
+                Ms[26] = E0;
+                for (int q = 0; q < 3; ++q) Ms[27 + q] = rawt[1 + q];
+                derive(I, cen, n0, f);
+                if (I.jmom_mode == 1 && (int)step >= I.avg_start) {
+                    const double ne = avg_window(I.n_avg, nsamp);
+                    double A[NMOM], ma[NMOM];
+                    for (int q = 0; q < NMOM; ++q) {
+                        double* Ag = I.avgs + (size_t)q * I.ncell + c;
+                        A[q] = (ne - 1.0) / ne * *Ag + 1.0 / ne * rawt[q];
+                        *Ag = A[q];
+                    }
+                    if (f.valid) {
+                        centred_from_raw(A, ma);
+                        CellF fa;
+                        derive(I, ma, 2, fa);
+                        for (int q = 0; q < 6; ++q) f.s[q] = fa.valid ? fa.s[q] : 0.0;
+                        for (int q = 0; q < 3; ++q) f.h[q] = fa.valid ? fa.h[q] : 0.0;
+                    }
+                }
+                if (f.valid) {
+                    // Eq. 33 divisors with P_ne^n
+                    const double Pn = I.pcur[c];
+                    const double da = 1.0 + I.dt * f.nu * Pn / 2.0;
+                    const double db = 1.0 + I.dt * f.nu * I.Pr * Pn / 2.0;
+                    for (int q = 0; q < 6; ++q) f.s[q] /= da;
+                    for (int q = 0; q < 3; ++q) f.h[q] /= db;
+                }
+            }
+            __syncthreads();
+        }
+        mark(1);
+        int flags = 0;
+        if (dg && tid == 0) {
+            dg[D_M0] = Ms[0];
+            dg[D_P0X] = Ms[27];
+            dg[D_P0Y] = Ms[28];
+            dg[D_P0Z] = Ms[29];
+            dg[D_E0] = Ms[26];
+            dg[D_MARG_SEL] = dg[D_MARG_ROUND] = dg[D_MARG_CNT] = __builtin_inf();
+        }
+        if (!f.valid) {
+            flags |= F_SKIP;
+        } else {
+            const double Pn = I.pcur[c];
+            double mcnt = __builtin_inf();
+            // step 4
+            const int n4 = spawn_r(I, P, L, 4, c, ix, iy, step, f, Pn, n0, n0, tid, &errbits,
+                                   &mcnt);
+            const int nl = n0 + n4;
+            mark(2);
+            // step 5
+            const double psel = -expm1(-f.x);
+            double ss[2] = {0.0, 0.0};
+            double msel = __builtin_inf();
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int j = k * NT + tid;
+                if (j < nl) {
+                    uint32_t r[4];
+                    draw(I, step, PUR_SELECT, 0u, (uint32_t)c, (uint32_t)j, r);
+                    const double u = uni_d(r[0], I.prec);
+                    const bool sel = u < psel;
+                    msel = fmin(msel, fabs(u - psel));
+                    P.key[k] = (r[1] & 0xFFFFF800u) | (uint32_t)j;
+                    if (sel) {
+                        P.st[k] = (P.st[k] & ~0xFFu) | FT_SEL;
+                        ss[0] += (double)P.w[k];
+                        ss[1] += 1.0;
+                    }
+                }
+            }
+            bsum(ss, L.red, tid);
+            if (dg) msel = bmin(msel, L.red, tid);
+            const double S = ss[0];
+            const int ns = (int)ss[1];
+            int nusp = (int)floor(S + 0.5);
+            if (nusp < 0) nusp = 0;
+            if (nusp > ns) nusp = ns;
+            mark(3);
+            uint32_t thr = 0;
+            if (nusp > 0 && nusp < ns) thr = kth_key_r(P, L, nusp, tid);
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                if (fate(P, k) == FT_SEL)
+                    P.st[k] = (P.st[k] & ~0xFFu) |
+                              ((nusp == ns || (nusp > 0 && P.key[k] <= thr)) ? FT_REASSIGN
+                                                                             : FT_DELETE);
+            mark(4);
+            // step 6
+            double fbs[1] = {0.0};
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                if (fate(P, k) == FT_REASSIGN) {
+                    fbs[0] += (double)resample_one(I, c, k * NT + tid, step, f, Pn, P.c0[k],
+                                                   P.c1[k], P.c2[k]);
+                    P.w[k] = (real)1.0;
+                }
+            mark(5);
+            // step 7
+            const int n7 = spawn_r(I, P, L, 7, c, ix, iy, step, f, Pn, nl, nl, tid, &errbits,
+                                   &mcnt);
+            nphys = nl + n7;
+            mark(6);
+            // conservation of the cell's mass, momentum and energy
+            double WrOut = 0.0, s2Out = 0.0;
+            if (I.conserve_mode == 0) {
+                double cs[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) cs[q] = 0.0;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const int fk = fate(P, k);
+                    const double w = (double)P.w[k];
+                    const double c0 = (double)P.c0[k], c1 = (double)P.c1[k];
+                    const double c2 = (double)P.c2[k];
+                    if (fk == FT_KEEP) {
+                        cs[0] += w;
+                        cs[1] += w * c0;
+                        cs[2] += w * c1;
+                        cs[3] += w * c2;
+                        cs[4] += 0.5 * w * (c0 * c0 + c1 * c1 + c2 * c2);
+                    } else if (fk == FT_REASSIGN) {
+                        cs[5] += c0;
+                        cs[6] += c1;
+                        cs[7] += c2;
+                    }
+                }
+                bsum(cs, L.red, tid);
+                if (nusp == 0) {
+                    flags |= F_NOUSP;
+                } else {
+                    const double M0 = Ms[0];
+                    const double Wr = (M0 - cs[0]) / nusp;
+                    WrOut = Wr;
+                    if (!(Wr > 0.0)) {
+                        flags |= F_FAILMASS;
+                    } else {
+                        const double MR = Wr * nusp;
+                        double a[3], cb[3];
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            a[q] = (Ms[27 + q] - cs[1 + q]) / MR;
+                            cb[q] = cs[5 + q] / nusp;
+                        }
+                        double dd[1] = {0.0};
+#pragma unroll
+                        for (int k = 0; k < PPT; ++k)
+                            if (fate(P, k) == FT_REASSIGN) {
+                                const double e0 = (double)P.c0[k] - cb[0];
+                                const double e1 = (double)P.c1[k] - cb[1];
+                                const double e2 = (double)P.c2[k] - cb[2];
+                                dd[0] += e0 * e0 + e1 * e1 + e2 * e2;
+                            }
+                        bsum(dd, L.red, tid);
+                        const double D = dd[0];
+                        const double a2 = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+                        double sc = 1.0;
+                        if (nusp >= 2 && D > 0.0) {
+                            const double s2 = (Ms[26] - cs[4] - 0.5 * MR * a2) / (0.5 * Wr * D);
+                            s2Out = s2;
+                            if (s2 > 0.0) sc = sqrt(s2);
+                            else flags |= F_FAILENERGY;
+                        } else {
+                            flags |= F_FAILENERGY;
+                        }
+#pragma unroll
+                        for (int k = 0; k < PPT; ++k)
+                            if (fate(P, k) == FT_REASSIGN) {
+                                P.c0[k] = (real)(a[0] + sc * ((double)P.c0[k] - cb[0]));
+                                P.c1[k] = (real)(a[1] + sc * ((double)P.c1[k] - cb[1]));
+                                P.c2[k] = (real)(a[2] + sc * ((double)P.c2[k] - cb[2]));
+                                P.w[k] = (real)Wr;
+                            }
+                    }
+                }
+            }
+            double fbt[1] = {fbs[0]};
+            bsum(fbt, L.red, tid);
+            mark(7);
+            // logical slots of the survivors (slot order), step-7 particles last
+            {
+                bool alive[PPT];
+                int pre[PPT];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) alive[k] = fate(P, k) <= FT_REASSIGN;
+                nlog = phys_scan(alive, pre, L.wtot, tid);
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+                    if (alive[k]) P.st[k] = (P.st[k] & 0xFFu) | ((uint32_t)pre[k] << 8);
+            }
+            if (nl + n7 > I.max_ppc) errbits |= ERR_CAPACITY;
+            mark(8);
+            if (dg && tid == 0) {
+                dg[D_N4] = n4;
+                dg[D_PSEL] = psel;
+                dg[D_MARG_SEL] = msel;
+                dg[D_MARG_ROUND] = fabs(S - (floor(S) + 0.5));
+                dg[D_SSEL] = S;
+                dg[D_NSEL] = ns;
+                dg[D_NUSP] = nusp;
+                dg[D_NDEL] = ns - nusp;
+                dg[D_N7] = n7;
+                dg[D_CHOLFB] = fbt[0];
+                dg[D_MARG_CNT] = mcnt;
+                dg[D_WR] = WrOut;
+                dg[D_S2] = s2Out;
+            }
+        }
+        // step 8: moments of f^{n+1}, Eq. 34 averages
+        {
+            double cen1[NMOM], raw1[NMOM], E1;
+            moments_r(P, L, tid, cen1, raw1, &E1);
+            if (tid == 0) {
+                I.cnt[c] = nlog;
+                const double ne = avg_window(I.n_avg, nsamp);
+                for (int q = 0; q < NMOM; ++q) {
+                    Ms[q] = cen1[q];
+                    I.mom[(size_t)q * I.ncell + c] = cen1[q];
+                    I.raw[(size_t)q * I.ncell + c] = raw1[q];
+                    if ((int)step >= I.avg_start) {
+                        double* A = I.avg + (size_t)q * I.ncell + c;
+                        *A = (ne - 1.0) / ne * *A + 1.0 / ne * raw1[q];
+                        Ms[13 + q] = *A;
+                    } else {
+                        Ms[13 + q] = I.avg[(size_t)q * I.ncell + c];
+                    }
+                }
+                if (dg) {
+                    dg[D_FLAGS] = flags;
+                    dg[D_NOUT] = nlog;
+                    dg[D_M1] = raw1[0];
+                    dg[D_P1X] = raw1[1];
+                    dg[D_P1Y] = raw1[2];
+                    dg[D_P1Z] = raw1[3];
+                    dg[D_E1] = E1;
+                }
+            }
+        }
+        mark(9);
+    } else if (mode & MODE_MOMENTS) {
+        double cen1[NMOM], raw1[NMOM], E1;
+        moments_r(P, L, tid, cen1, raw1, &E1);
+        if (tid == 0) {
+            I.cnt[c] = nlog;
+            for (int q = 0; q < NMOM; ++q) {
+                Ms[q] = cen1[q];
+                I.mom[(size_t)q * I.ncell + c] = cen1[q];
+                I.raw[(size_t)q * I.ncell + c] = raw1[q];
+                Ms[13 + q] = I.avg[(size_t)q * I.ncell + c];
+            }
+        }
+    }
+
+    real* out[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) out[q] = (real*)I.pc[1 - cur][q];
+    uint32_t* tout = I.tab[1 - cur] + (size_t)c * (nb + 1);
+    const size_t rbase = (size_t)c * I.cap;
+
+    if (mode & MODE_MOVE) {
+        const uint32_t mstep = (mode & MODE_RELAX) ? step + 1 : step;
+        // cell scalars of f^{n+1} (or f^n when no relaxation ran) for step 2
+        if (tid == 0) {
+            double m[NMOM], A[NMOM];
+            for (int q = 0; q < NMOM; ++q) {
+                m[q] = (mode & (MODE_RELAX | MODE_MOMENTS)) ? Ms[q]
+                                                           : I.mom[(size_t)q * I.ncell + c];
+                A[q] = (mode & (MODE_RELAX | MODE_MOMENTS)) ? Ms[13 + q]
+                                                           : I.avg[(size_t)q * I.ncell + c];
+            }
+            derive(I, m, nlog, f);
+            const int ns_after =
+                nsamp + (((mode & MODE_RELAX) && (int)step >= I.avg_start) ? 1 : 0);
+            if (I.jmom_mode == 1 && ns_after > 0 && f.valid) {
+                double ma[NMOM];
+                centred_from_raw(A, ma);
+                CellF fa;
+                derive(I, ma, 2, fa);
+                for (int q = 0; q < 6; ++q) f.s[q] = fa.valid ? fa.s[q] : 0.0;
+                for (int q = 0; q < 3; ++q) f.h[q] = fa.valid ? fa.h[q] : 0.0;
+            }
+        }
+        __syncthreads();
+        const double P2 = (mode & MODE_RELAX) ? I.pcur[c] : I.pprev[c];
+        double mc2 = __builtin_inf();
+        // step 2 of the next time level
+        const int n2 = spawn_r(I, P, L, 2, c, ix, iy, mstep, f, P2, nphys, nlog, tid, &errbits,
+                               &mc2);
+        nphys += n2;
+        nlog += n2;
+        mark(10);
+        // step 3: advect, walls, destination bin (or far list)
+        int clamps = 0;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            uint32_t b = FAR_BIN;
+            if (fate(P, k) <= FT_REASSIGN) {
+                real px = DIM == 2 ? P.x[k] : (real)0;
+                real py = P.y[k];
+                const int slot = (int)(P.st[k] >> 8);
+                const int d = advect<real, DIM>(I, px, py, P.c0[k], P.c1[k], P.c2[k], c, slot,
+                                                mstep, &clamps);
+                if (DIM == 2) P.x[k] = px;
+                P.y[k] = py;
+                const int dx_ = d % I.nx, dy_ = d / I.nx;
+                const int oy = min_image(iy - dy_, I.ny, per_y);
+                const int ox = DIM == 2 ? min_image(ix - dx_, I.nx, per_x) : 0;
+                if (oy < -I.Ky || oy > I.Ky || ox < -I.Kx || ox > I.Kx) {
+                    const int e = atomicAdd(&I.far_n[1 - cur], 1);
+                    if (e < I.far_cap) {
+                        uint32_t* fm = I.far_meta[1 - cur] + 3 * (size_t)e;
+                        fm[0] = (uint32_t)d;
+                        fm[1] = ((uint32_t)(oy + 32768) << 16) | (uint32_t)(ox + 32768);
+                        fm[2] = (uint32_t)slot;
+                        real* const* fo = (real* const*)I.far_pc[1 - cur];
+                        if (DIM == 2) fo[0][e] = px;
+                        fo[1][e] = py;
+                        fo[2][e] = P.c0[k];
+                        fo[3][e] = P.c1[k];
+                        fo[4][e] = P.c2[k];
+                        fo[5][e] = P.w[k];
+                    } else {
+                        errbits |= ERR_WINDOW;
+                    }
+                } else {
+                    b = (uint32_t)((oy + I.Ky) * I.nbx + (ox + I.Kx));
+                }
+            }
+            P.key[k] = b;
+        }
+        mark(11);
+        // stable ranks by bin over physical positions (tiles of 64)
+        const int ntl = (nphys + 63) / 64;
+        for (int q = tid; q < ntl * nb; q += NT) L.tiles[q] = 0;
+        __syncthreads();
+        const int lane = tid & 63;
+        uint32_t rank[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int j = k * NT + tid;
+            const bool act = P.key[k] != (uint32_t)FAR_BIN;
+            const int b = (int)P.key[k];
+            const int tile = j >> 6;
+            rank[k] = 0;
+            uint64_t rem = __ballot(act);
+            while (rem) {
+                const int leader = __ffsll((unsigned long long)rem) - 1;
+                const int bv = __builtin_amdgcn_readlane(b, leader);
+                const uint64_t mm = __ballot(act && b == bv);
+                if (lane == leader) L.tiles[tile * nb + bv] = (uint16_t)__popcll(mm);
+                if (act && b == bv) rank[k] = (uint32_t)__popcll(mm & lanemask_lt(lane));
+                rem &= ~mm;
+            }
+        }
+        __syncthreads();
+        for (int b = tid; b < nb; b += NT) {
+            uint32_t s = 0;
+            for (int t = 0; t < ntl; ++t) s += L.tiles[t * nb + b];
+            L.boff[b] = s;
+        }
+        __syncthreads();
+        wave0_scan(L.boff, nb, tid);
+        __syncthreads();
+        for (int b = tid; b < nb; b += NT) {
+            uint32_t run = L.boff[b];
+            for (int t = 0; t < ntl; ++t) {
+                const uint32_t v = L.tiles[t * nb + b];
+                L.tiles[t * nb + b] = (uint16_t)run;
+                run += v;
+            }
+        }
+        __syncthreads();
+        mark(12);
+        // write-out: each particle straight from its registers
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (P.key[k] != (uint32_t)FAR_BIN) {
+                const int j = k * NT + tid;
+                const uint32_t pos = (uint32_t)L.tiles[(j >> 6) * nb + P.key[k]] + rank[k];
+                if (DIM == 2) out[0][rbase + pos] = P.x[k];
+                out[1][rbase + pos] = P.y[k];
+                out[2][rbase + pos] = P.c0[k];
+                out[3][rbase + pos] = P.c1[k];
+                out[4][rbase + pos] = P.c2[k];
+                out[5][rbase + pos] = P.w[k];
+            }
+        }
+        for (int b = tid; b <= nb; b += NT) tout[b] = L.boff[b];
+        mark(13);
+        if (dg) {
+            double cl[1] = {(double)clamps};
+            bsum(cl, L.red, tid);
+            if (tid == 0) {
+                dg[D_N2] = n2;
+                dg[D_CLAMP] = cl[0];
+                dg[D_MARG_CNT2] = mc2;
+            }
+        }
+    } else {
+        // stay layout: every live particle at its logical slot of its own cell
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            if (fate(P, k) <= FT_REASSIGN) {
+                const uint32_t pos = P.st[k] >> 8;
+                if (DIM == 2) out[0][rbase + pos] = P.x[k];
+                out[1][rbase + pos] = P.y[k];
+                out[2][rbase + pos] = P.c0[k];
+                out[3][rbase + pos] = P.c1[k];
+                out[4][rbase + pos] = P.c2[k];
+                out[5][rbase + pos] = P.w[k];
+            }
+        }
+        const int centre = I.Ky * I.nbx + I.Kx;
+        for (int b = tid; b <= nb; b += NT) tout[b] = b <= centre ? 0u : (uint32_t)nlog;
+    }
+    if (nlog > I.max_ppc || nphys > CAP) errbits |= ERR_CAPACITY;
+    const uint64_t em = __ballot(errbits != 0);
+    if (em) {
+        uint32_t e = errbits;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) e |= __shfl_xor(e, o, 64);
+        if ((tid & 63) == 0) atomicOr(&I.ctl[CTL_ERR], (int)e);
+    }
+}
+
+template <typename real, int DIM, int PPT>
+__global__ void __launch_bounds__(NT, 2) cell_kernel(Batch B)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x;
+    for (int g = blockIdx.x; g < B.ncells; g += gridDim.x) {
+        int lo = 0, hi = B.ninst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (B.base[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        process_cell_r<real, DIM, PPT>(B.inst[lo], g - B.base[lo], B.mode, smem, tid);
+        __syncthreads();
+    }
+}
+
+#define USP_CELL_INST(R, D, PPT) template __global__ void cell_kernel<R, D, PPT>(Batch);
+USP_CELL_INST(float, 1, 1)
+USP_CELL_INST(float, 1, 2)
+USP_CELL_INST(float, 1, 4)
+USP_CELL_INST(float, 1, 8)
+USP_CELL_INST(float, 2, 1)
+USP_CELL_INST(float, 2, 2)
+USP_CELL_INST(float, 2, 4)
+USP_CELL_INST(float, 2, 8)
+USP_CELL_INST(double, 1, 1)
+USP_CELL_INST(double, 1, 2)
+USP_CELL_INST(double, 1, 4)
+USP_CELL_INST(double, 1, 8)
+USP_CELL_INST(double, 2, 1)
+USP_CELL_INST(double, 2, 2)
+USP_CELL_INST(double, 2, 4)
+USP_CELL_INST(double, 2, 8)
+
+}  // namespace usp

@@ -7,7 +7,8 @@
 namespace usp {
 
 constexpr int NMOM = 13;   // centred moments / raw sums per cell
-constexpr int NDIAG = 32;  // per-cell diagnostic record
+constexpr int NDIAG = 48;  // per-cell diagnostic record
+constexpr int NDIAG_STEP = 32;  // slots describing the last step; then phase cycle counters
 constexpr int MAX_BINS = 256;
 constexpr int MAX_PPC = 2048;
 constexpr int FAR_LDS = 128;  // far arrivals one cell can take per step
@@ -89,29 +90,34 @@ struct Batch {
     int ninst;
     int ncells;           // total cells
     int mode;
-    int cap_lds;          // particle slots of the LDS list
 };
 
-// LDS bytes of the cell kernel for a given list capacity / state precision
-inline size_t lds_bytes(int cap, int real_bytes, int dim, int nb, int nthreads)
+// LDS bytes of the cell kernel for `cap` particle slots and `nb` bins (the
+// same carving as the kernel: every array rounded up to 16 bytes)
+inline size_t lds_bytes(int cap, int nb)
 {
+    auto r16 = [](size_t b) { return (b + 15) & ~(size_t)15; };
     size_t b = 0;
-    b += (size_t)(dim + 4) * cap * real_bytes;   // positions, velocities, weight
-    b += (size_t)cap * 4;                       // keys / inverse map
-    b += (size_t)cap * 4;                       // time-sample words
-    b += (size_t)cap * 2 * 2;                   // slots, bins
-    b += (size_t)cap;                           // fates
-    b = (b + 15) & ~(size_t)15;
-    b += (size_t)(nthreads / 64) * 24 * 8;      // reductions
-    b += 256 * 4;                               // histogram
-    b += (size_t)((cap + 63) / 64) * nb * 2;    // tile counts
-    b = (b + 15) & ~(size_t)15;
-    b += (size_t)(nb + 1) * 4 * 4;              // runs / bin offsets
-    b = (b + 15) & ~(size_t)15;
-    b += (size_t)FAR_LDS * (8 + 4 + 4 + 4) + 16;  // far arrivals
-    b = (b + 15) & ~(size_t)15;
-    b += 64 * 8;                                // scalars
+    b += r16((size_t)cap * 4);                  // gather map
+    b += r16((size_t)(cap / 64) * nb * 2);      // bin tile counts
+    b += r16(256 * 4) + r16(64 * 4);            // histogram, scan totals
+    b += r16(4 * 24 * 8);                       // reductions
+    b += 4 * r16((size_t)(nb + 1) * 4);         // runs, bin offsets
+    b += r16((size_t)FAR_LDS * 8) + 3 * r16((size_t)FAR_LDS * 4) + r16(16);  // far arrivals
+    b += r16(64 * 8);                           // scalars
+    b += r16(256) + r16(32 * 8);                // cell scalars, moments
     return b;
+}
+
+// particles per thread of the cell kernel for a largest cell of max_ppc
+// particles (256 threads; room for the step-2 particles of a full cell)
+inline int pick_ppt(int max_ppc)
+{
+    const int need = max_ppc + max_ppc / 8 + 1;
+    if (need <= 256) return 1;
+    if (need <= 512) return 2;
+    if (need <= 1024) return 4;
+    return 8;
 }
 
 }  // namespace usp

@@ -158,11 +158,37 @@ __device__ __forceinline__ double avg_window(int n_avg, int n_samples)
 // ---------------------------------------------------------------------------
 // Wavefront / workgroup reductions (deterministic: fixed butterfly order)
 // ---------------------------------------------------------------------------
+// one DPP lane move of a double (two 32-bit moves); lanes without a source,
+// or outside ROWMASK, receive +0.0
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWMASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double x, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront (all lanes active): row shifts by
+// 1, 2, 4, 8 leave each 16-lane row's total in its lane 15; two row
+// broadcasts carry them to lane 63, which is then read by every lane.  The
+// order of additions is fixed, so the result is deterministic and identical
+// in all lanes.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_d<0x111, 0xF>(v);  // row_shr:1
+    v += dpp_d<0x112, 0xF>(v);  // row_shr:2
+    v += dpp_d<0x114, 0xF>(v);  // row_shr:4
+    v += dpp_d<0x118, 0xF>(v);  // row_shr:8
+    v += dpp_d<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_d<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return readlane_d(v, 63);
 }
 
 __device__ __forceinline__ double wave_min(double v)
@@ -243,5 +269,148 @@ __device__ __forceinline__ int ordered_compact(int n, int tid, int nt, uint32_t*
     }
     return base;
 }
+
+
+__device__ __forceinline__ int wrap(int i, int n) { return ((i % n) + n) % n; }
+
+// signed cell offset along an axis; across a periodic axis the nearest image
+__device__ __forceinline__ int min_image(int d, int n, bool periodic)
+{
+    if (!periodic) return d;
+    int r = wrap(d, n);
+    if (r > n - n / 2 - 1) r -= n;
+    return r;
+}
+
+// basis (1, C / sqrt(theta), C^2 / (2 theta) - 3/2) of the zero-moment
+// projection of an added batch
+__device__ __forceinline__ void psi5(double c0, double c1, double c2, const double* U, double sq,
+                                     double theta, double* psi)
+{
+    const double C0 = c0 - U[0], C1 = c1 - U[1], C2 = c2 - U[2];
+    psi[0] = 1.0;
+    psi[1] = C0 / sq;
+    psi[2] = C1 / sq;
+    psi[3] = C2 / sq;
+    psi[4] = (C0 * C0 + C1 * C1 + C2 * C2) / (2.0 * theta) - 1.5;
+}
+
+// ---------------------------------------------------------------------------
+// Step 3 for one particle: free flight by one fused multiply-add in the state
+// precision; particles leaving the domain are traced wall to wall in double.
+// Returns the destination cell.
+// ---------------------------------------------------------------------------
+// Wall-to-wall trace of a particle that leaves the domain during the step
+// (double precision); rare, so kept out of line.
+template <typename real, int DIM>
+__device__ __noinline__ void wall_trace(const InstDev& I, real& px, real& py, real& c0, real& c1,
+                                        real& c2, int src_cell, int slot, uint32_t step,
+                                        int* clamp)
+{
+    const double lo[2] = {I.x0, I.y0}, hi[2] = {I.x1, I.y1};
+    {
+        double pos[2] = {(double)px, (double)py};
+        double vel[3] = {(double)c0, (double)c1, (double)c2};
+        double tl = I.dt;
+        const int a0 = DIM == 2 ? 0 : 1;
+        for (int hit = 0;; ++hit) {
+            if (hit == 16) {
+                for (int a = a0; a < 2; ++a) {
+                    if (pos[a] < lo[a]) pos[a] = lo[a];
+                    if (pos[a] > hi[a]) pos[a] = hi[a];
+                }
+                ++*clamp;
+                break;
+            }
+            double te = __builtin_inf();
+            int ax = -1, sd = 0;
+            for (int a = a0; a < 2; ++a) {
+                double t;
+                int side;
+                if (vel[a] > 0.0) {
+                    t = (hi[a] - pos[a]) / vel[a];
+                    side = 1;
+                } else if (vel[a] < 0.0) {
+                    t = (lo[a] - pos[a]) / vel[a];
+                    side = 0;
+                } else {
+                    continue;
+                }
+                if (t < te) {
+                    te = t;
+                    ax = a;
+                    sd = side;
+                }
+            }
+            if (!(te < tl)) {
+                for (int a = a0; a < 2; ++a) pos[a] += vel[a] * tl;
+                break;
+            }
+            if (te < 0.0) te = 0.0;
+            for (int a = a0; a < 2; ++a) pos[a] += vel[a] * te;
+            pos[ax] = sd ? hi[ax] : lo[ax];
+            tl -= te;
+            const int face = 2 * ax + sd;
+            const int kind = I.face_kind[face];
+            if (kind == 1) {
+                vel[ax] = -vel[ax];
+            } else if (kind == 2) {
+                pos[ax] = sd ? lo[ax] : hi[ax];
+            } else {
+                uint32_t r[4];
+                draw(I, step, PUR_WALL, (uint32_t)hit, (uint32_t)src_cell, (uint32_t)slot, r);
+                const double thw = I.kB * I.face_T[face] / I.m;
+                const double u0 = uni_d(r[0], I.prec), u1 = uni_d(r[1], I.prec);
+                const double u2 = uni_d(r[2], I.prec);
+                const double vn = sqrt(-2.0 * thw * log(u0));
+                const double rad = sqrt(-2.0 * log(u1));
+                double s, c;
+                sincospi(2.0 * u2, &s, &c);
+                const int vi = ax;
+                const int ta = vi == 0 ? 1 : 0, tb = 2;
+                const double* uw = I.face_u + 3 * face;
+                const double sth = sqrt(thw);
+                vel[vi] = sd ? -vn : vn;
+                vel[ta] = uw[ta] + sth * (rad * c);
+                vel[tb] = uw[tb] + sth * (rad * s);
+            }
+        }
+        if (DIM == 2) px = (real)pos[0];
+        py = (real)pos[1];
+        c0 = (real)vel[0];
+        c1 = (real)vel[1];
+        c2 = (real)vel[2];
+    }
+}
+
+template <typename real, int DIM>
+__device__ __forceinline__ int advect(const InstDev& I, real& px, real& py, real& c0, real& c1,
+                                      real& c2, int src_cell, int slot, uint32_t step, int* clamp)
+{
+    const real dtr = (real)I.dt;
+    real np0 = px, np1;
+    if (DIM == 2) np0 = fma(c0, dtr, px);
+    np1 = fma(c1, dtr, py);
+    bool inside = ((double)np1 >= I.y0) && ((double)np1 < I.y1);
+    if (DIM == 2) inside = inside && ((double)np0 >= I.x0) && ((double)np0 < I.x1);
+    if (inside) {
+        px = np0;
+        py = np1;
+    } else {
+        wall_trace<real, DIM>(I, px, py, c0, c1, c2, src_cell, slot, step, clamp);
+    }
+    if (I.accel[0] != 0.0) c0 = c0 + (real)(I.accel[0] * I.dt);
+    if (I.accel[1] != 0.0) c1 = c1 + (real)(I.accel[1] * I.dt);
+    if (I.accel[2] != 0.0) c2 = c2 + (real)(I.accel[2] * I.dt);
+    int iy = (int)floor(((double)py - I.y0) * I.inv_dy);
+    iy = iy < 0 ? 0 : (iy > I.ny - 1 ? I.ny - 1 : iy);
+    int ix = 0;
+    if (DIM == 2) {
+        ix = (int)floor(((double)px - I.x0) * I.inv_dx);
+        ix = ix < 0 ? 0 : (ix > I.nx - 1 ? I.nx - 1 : ix);
+    }
+    return iy * I.nx + ix;
+}
+
 
 }  // namespace usp

@@ -20,7 +20,7 @@
 #include "usp_common.h"
 
 namespace usp {
-template <typename real, int DIM>
+template <typename real, int DIM, int PPT>
 __global__ void cell_kernel(Batch B);
 template <typename real, int DIM>
 __global__ void init_kernel(Batch B, const double* init_n, const double* init_u,
@@ -197,23 +197,34 @@ usp_status with_kernel(int prec, int dim, F f)
     return f((double*)nullptr, std::integral_constant<int, 2>());
 }
 
-usp_status launch_cell(usp_ctx* ctx, const Batch& B, int prec, int dim, int max_nb, int nthreads)
+template <typename real, int D>
+const void* cell_kernel_for(int ppt)
 {
-    const size_t lds = lds_bytes(B.cap_lds, prec == 32 ? 4 : 8, dim, max_nb, nthreads);
+    switch (ppt) {
+        case 1: return (const void*)cell_kernel<real, D, 1>;
+        case 2: return (const void*)cell_kernel<real, D, 2>;
+        case 4: return (const void*)cell_kernel<real, D, 4>;
+        default: return (const void*)cell_kernel<real, D, 8>;
+    }
+}
+
+usp_status launch_cell(usp_ctx* ctx, const Batch& B, int prec, int dim, int max_nb, int ppt)
+{
+    const size_t lds = lds_bytes(ppt * 256, max_nb);
     return with_kernel(prec, dim, [&](auto* rp, auto dimc) -> usp_status {
         using real = std::remove_pointer_t<decltype(rp)>;
         constexpr int D = decltype(dimc)::value;
-        auto kern = cell_kernel<real, D>;
-        HIPCHK(ctx, hipFuncSetAttribute((const void*)kern,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        const void* kern = cell_kernel_for<real, D>(ppt);
+        HIPCHK(ctx, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds));
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (ctx->timing) {
             HIPCHK(ctx, hipEventCreate(&e0));
             HIPCHK(ctx, hipEventCreate(&e1));
             HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
         }
-        hipLaunchKernelGGL(kern, dim3(B.ncells), dim3(nthreads), lds, ctx->stream, B);
-        HIPCHK(ctx, hipGetLastError());
+        void* args[] = {(void*)&B};
+        HIPCHK(ctx, hipLaunchKernel(kern, dim3(B.ncells), dim3(256), args, lds, ctx->stream));
         if (ctx->timing) {
             HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
             ctx->events.emplace_back(e0, e1);
@@ -247,7 +258,6 @@ Batch single_batch(Instance* in, int mode)
     B.ninst = 1;
     B.ncells = in->h.ncell;
     B.mode = mode;
-    B.cap_lds = in->h.cap;
     return B;
 }
 
@@ -277,7 +287,7 @@ usp_status err_status(usp_ctx* ctx, int e)
 usp_status finish_state(usp_ctx* ctx, Instance* in)
 {
     Batch B = single_batch(in, MODE_MOMENTS);
-    usp_status s = launch_cell(ctx, B, in->h.prec, in->h.dim, in->h.nb, ctx->block);
+    usp_status s = launch_cell(ctx, B, in->h.prec, in->h.dim, in->h.nb, pick_ppt(in->h.max_ppc));
     if (s) return s;
     if ((s = launch_fields(ctx, B, 1))) return s;
     return launch_ctl(ctx, B, 0);
@@ -499,8 +509,7 @@ usp_status usp_set_block(usp_ctx* ctx, int threads)
 {
     if (!ctx) return USP_EINVAL;
     if (threads == 0) threads = 256;
-    if (threads < 64 || threads > 256 || threads % 64)
-        return fail(ctx, USP_EINVAL, "threads must be a multiple of 64 in [64, 256]");
+    if (threads != 256) return fail(ctx, USP_EINVAL, "the cell kernel runs 256 threads per cell");
     ctx->block = threads;
     return USP_OK;
 }
@@ -549,20 +558,20 @@ usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps)
         B.base = ctx->bbase;
         B.ninst = (int)sel.size();
         B.ncells = 0;
-        B.cap_lds = 0;
-        int max_nb = 0;
+        int max_nb = 0, max_ppc = 0;
         for (int id : sel) {
             B.ncells += ctx->inst[id]->h.ncell;
-            B.cap_lds = std::max(B.cap_lds, ctx->inst[id]->h.cap);
+            max_ppc = std::max(max_ppc, ctx->inst[id]->h.max_ppc);
             max_nb = std::max(max_nb, ctx->inst[id]->h.nb);
         }
+        const int ppt = pick_ppt(max_ppc);
         usp_status s;
         B.mode = MODE_MOVE;
-        if ((s = launch_cell(ctx, B, prec, dim, max_nb, ctx->block))) return s;
+        if ((s = launch_cell(ctx, B, prec, dim, max_nb, ppt))) return s;
         if ((s = launch_ctl(ctx, B, 0))) return s;
         for (int k = 0; k < nsteps; ++k) {
             B.mode = k + 1 < nsteps ? (MODE_RELAX | MODE_MOVE) : MODE_RELAX;
-            if ((s = launch_cell(ctx, B, prec, dim, max_nb, ctx->block))) return s;
+            if ((s = launch_cell(ctx, B, prec, dim, max_nb, ppt))) return s;
             if ((s = launch_fields(ctx, B, 0))) return s;
             if ((s = launch_ctl(ctx, B, 1))) return s;
         }

@@ -138,6 +138,12 @@ class Problem:
     def expected_particles(self) -> int:
         return int(np.sum(np.floor(self.init_n * self.vcell / self.Np + 0.5)))
 
+    def with_capacity(self, factor: float = 3.0) -> "Problem":
+        """max_ppc = factor x the fullest initial cell (multiple of 64, <= 2048)"""
+        full = float(np.max(np.floor(self.init_n * self.vcell / self.Np + 0.5)))
+        cap = int(min(2048, max(64, -(-int(factor * full) // 64) * 64)))
+        return self.replace(max_ppc=cap)
+
 
 def _faces_1d(lo: Face, hi: Face) -> List[Face]:
     # x faces are inert in 1-D
@@ -166,14 +172,14 @@ def couette_1d(Kn=0.1, U_w=100.0, T_w=273.0, ncell=100, ppc=100, dt_over_tau=1.0
     n0, rho0, lam0, tau0 = standard_state(gas, T_w)
     H = lam0 / Kn
     g = _grid_1d(ncell, H)
-    return Problem(name=name, gas=gas, **g,
+    return _sized(Problem(name=name, gas=gas, **g,
                    faces=_faces_1d(Face(BC_DIFFUSE, T_w, (-U_w, 0.0, 0.0)),
                                    Face(BC_DIFFUSE, T_w, (U_w, 0.0, 0.0))),
                    accel=(0.0, 0.0, 0.0), dt=dt_over_tau * tau0, Np=n0 * g["vcell"] / ppc,
                    init_n=np.full(ncell, n0), init_u=np.zeros((ncell, 3)),
                    init_T=np.full(ncell, T_w), precision=precision, seed=seed,
                    pne_mode=pne_mode,
-                   meta=dict(H=H, lam0=lam0, tau0=tau0, n0=n0, U_w=U_w, T_w=T_w, Kn=Kn))
+                   meta=dict(H=H, lam0=lam0, tau0=tau0, n0=n0, U_w=U_w, T_w=T_w, Kn=Kn)))
 
 
 def thermal_couette_1d(Kn=1e-3, dT=10.0, T_w=273.0, ncell=1000, ppc=500, dt_over_tau=5.0,
@@ -195,13 +201,13 @@ def thermal_couette_1d(Kn=1e-3, dT=10.0, T_w=273.0, ncell=1000, ppc=500, dt_over
     else:
         T = np.full(ncell, T_w)
     n = P_ATM / (gas.kB * T)
-    return Problem(name=name, gas=gas, **g,
+    return _sized(Problem(name=name, gas=gas, **g,
                    faces=_faces_1d(Face(BC_DIFFUSE, Tb), Face(BC_DIFFUSE, Tt)),
                    accel=(0.0, 0.0, 0.0), dt=dt_over_tau * tau0, Np=n0 * g["vcell"] / ppc,
                    init_n=n, init_u=np.zeros((ncell, 3)), init_T=T, precision=precision,
                    seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
                    spawn_projection=spawn_projection,
-                   meta=dict(H=H, lam0=lam0, tau0=tau0, n0=n0, T_bottom=Tb, T_top=Tt, Kn=Kn))
+                   meta=dict(H=H, lam0=lam0, tau0=tau0, n0=n0, T_bottom=Tb, T_top=Tt, Kn=Kn)))
 
 
 def sod_1d(Kn=1e-3, L=1.0, ncell=1000, mean_ppc=500, rho_ratio=8.0, p_ratio=10.0,
@@ -228,13 +234,13 @@ def sod_1d(Kn=1e-3, L=1.0, ncell=1000, mean_ppc=500, rho_ratio=8.0, p_ratio=10.0
     n = np.where(left, n_l, n_r)
     T = np.where(left, T_l, T_r)
     ppc_l = 2.0 * mean_ppc * rho_ratio / (rho_ratio + 1.0)
-    return Problem(name=name, gas=gas, **g,
+    return _sized(Problem(name=name, gas=gas, **g,
                    faces=_faces_1d(Face(BC_SPECULAR), Face(BC_SPECULAR)),
                    accel=(0.0, 0.0, 0.0), dt=dt_over_tau * tau_l, Np=n_l * g["vcell"] / ppc_l,
                    init_n=n, init_u=np.zeros((ncell, 3)), init_T=T, precision=precision,
                    seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
                    spawn_projection=spawn_projection,
-                   meta=dict(L=L, lam_l=lam_l, tau_l=tau_l, rho_l=rho_l, p_l=p_l, T_r=T_r, Kn=Kn))
+                   meta=dict(L=L, lam_l=lam_l, tau_l=tau_l, rho_l=rho_l, p_l=p_l, T_r=T_r, Kn=Kn)))
 
 
 def poiseuille_1d(Kn=1e-3, dpdx=4.0e6, T_w=273.0, ncell=100, ppc=500, dt_over_tau=5.0,
@@ -246,7 +252,7 @@ def poiseuille_1d(Kn=1e-3, dpdx=4.0e6, T_w=273.0, ncell=100, ppc=500, dt_over_ta
     n0, rho0, lam0, tau0 = standard_state(gas, T_w)
     H = lam0 / Kn
     g = _grid_1d(ncell, H)
-    return Problem(name=name, gas=gas, **g,
+    return _sized(Problem(name=name, gas=gas, **g,
                    faces=_faces_1d(Face(BC_DIFFUSE, T_w), Face(BC_DIFFUSE, T_w)),
                    accel=(dpdx / rho0, 0.0, 0.0), dt=dt_over_tau * tau0,
                    Np=n0 * g["vcell"] / ppc, init_n=np.full(ncell, n0),
@@ -254,7 +260,7 @@ def poiseuille_1d(Kn=1e-3, dpdx=4.0e6, T_w=273.0, ncell=100, ppc=500, dt_over_ta
                    precision=precision, seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
                    spawn_projection=spawn_projection,
                    meta=dict(H=H, lam0=lam0, tau0=tau0, rho0=rho0, n0=n0, dpdx=dpdx, T_w=T_w,
-                             Kn=Kn))
+                             Kn=Kn)))
 
 
 def cavity_2d(Kn=1e-3, n=128, ppc=200, U_lid=50.0, T_w=273.0, omega=0.81, precision=32,
@@ -270,13 +276,13 @@ def cavity_2d(Kn=1e-3, n=128, ppc=200, U_lid=50.0, T_w=273.0, omega=0.81, precis
     still = Face(BC_DIFFUSE, T_w)
     faces = [still, still, still, Face(BC_DIFFUSE, T_w, (U_lid, 0.0, 0.0))]
     nc = n * n
-    return Problem(name=name, gas=gas, dim=2, nx=n, ny=n, x0=0.0, x1=L, y0=0.0, y1=L, dx=d,
+    return _sized(Problem(name=name, gas=gas, dim=2, nx=n, ny=n, x0=0.0, x1=L, y0=0.0, y1=L, dx=d,
                    dy=d, inv_dx=n / L, inv_dy=n / L, vcell=d * d, faces=faces,
                    accel=(0.0, 0.0, 0.0), dt=0.3 * d / gas.mean_speed(T_w),
                    Np=n0 * d * d / ppc, init_n=np.full(nc, n0), init_u=np.zeros((nc, 3)),
                    init_T=np.full(nc, T_w), precision=precision, seed=seed, pne_mode=pne_mode,
                    jmom_mode=jmom_mode, spawn_projection=spawn_projection,
-                   meta=dict(L=L, lam0=lam0, tau0=tau0, n0=n0, U_lid=U_lid, Kn=Kn))
+                   meta=dict(L=L, lam0=lam0, tau0=tau0, n0=n0, U_lid=U_lid, Kn=Kn)))
 
 
 def homogeneous_box(ncell=64, ppc=1000, nu_dt=1.0, T=273.0, precision=64, seed=0,
@@ -289,12 +295,16 @@ def homogeneous_box(ncell=64, ppc=1000, nu_dt=1.0, T=273.0, precision=64, seed=0
     H = 100.0 * lam0
     g = _grid_1d(ncell, H)
     per = Face(BC_PERIODIC)
-    return Problem(name=name, gas=gas, **g, faces=_faces_1d(per, per),
+    return _sized(Problem(name=name, gas=gas, **g, faces=_faces_1d(per, per),
                    accel=(0.0, 0.0, 0.0), dt=nu_dt / nu, Np=n0 * g["vcell"] / ppc,
                    init_n=np.full(ncell, n0), init_u=np.zeros((ncell, 3)),
                    init_T=np.full(ncell, T), precision=precision, seed=seed,
                    pne_mode=PNE_FIXED, pne_fixed=pne,
-                   meta=dict(n0=n0, nu=nu, tau0=tau0, lam0=lam0, H=H))
+                   meta=dict(n0=n0, nu=nu, tau0=tau0, lam0=lam0, H=H)))
+
+
+def _sized(pb: Problem) -> Problem:
+    return pb.with_capacity()
 
 
 def config(name: str, **kw) -> Problem:

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libusp.so")
 NMOM = 13
 NCS = 4 * NMOM + 2
 NF = 18
-NDIAG = 32
+NDIAG = 48
 
 STATUS = {0: "USP_OK", -1: "USP_EINVAL", -2: "USP_ENOMEM", -3: "USP_ECAPACITY",
           -4: "USP_EWINDOW", -5: "USP_EDEVICE", -7: "USP_ESTATE", -8: "USP_ENOLIB"}
