@@ -26,8 +26,7 @@
 
 namespace usp {
 
-constexpr int NT = 256;
-constexpr int NW = NT / 64;
+constexpr int MAX_NW = 8;  // waves per workgroup at most (512 threads)
 constexpr int FAR_BIN = 0xFFFF;
 constexpr uint32_t FARBIT = 0x80000000u;
 
@@ -51,7 +50,9 @@ struct Lds {
     uint32_t* fcount;
     double* sc;
     CellF* f;      // cell scalars shared by the workgroup
-    double* mom;   // [0..12] centred, [13..25] raw, [26] energy, [27..29] momentum
+    double* mom;   // [0..12] centred, [13..25] averages, [26] energy, [27..29] momentum
+    double* pend;  // [0..12] raw sums, [13..25] J-moment averages, [26] count: stored
+                   // to HBM once the cell can no longer be handed to a larger shape
 };
 
 static_assert(sizeof(CellF) <= 256, "cell scalars must fit their LDS slot");
@@ -69,7 +70,7 @@ __device__ __forceinline__ Lds carve(unsigned char* sm, int cap, int nb)
     L.tiles = (uint16_t*)take((size_t)(cap / 64) * nb * 2);
     L.hist = (uint32_t*)take(256 * 4);
     L.wtot = (uint32_t*)take(64 * 4);
-    L.red = (double*)take((size_t)NW * 24 * 8);
+    L.red = (double*)take((size_t)MAX_NW * 24 * 8);
     L.run_pre = (uint32_t*)take((size_t)(nb + 1) * 4);
     L.run_src = (uint32_t*)take((size_t)(nb + 1) * 4);
     L.run_dst = (uint32_t*)take((size_t)(nb + 1) * 4);
@@ -82,12 +83,17 @@ __device__ __forceinline__ Lds carve(unsigned char* sm, int cap, int nb)
     L.sc = (double*)take(64 * 8);
     L.f = (CellF*)take(sizeof(CellF));
     L.mom = (double*)take(32 * 8);
+    L.pend = (double*)take(32 * 8);
     return L;
 }
 
-template <int K>
+// a value known to be equal in all lanes, made visibly uniform (scalar)
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <int NT, int K>
 __device__ __forceinline__ void bsum(double (&v)[K], double* red, int tid)
 {
+    constexpr int NW = NT / 64;
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
     const int lane = tid & 63, wave = tid >> 6;
@@ -105,8 +111,10 @@ __device__ __forceinline__ void bsum(double (&v)[K], double* red, int tid)
     }
 }
 
+template <int NT>
 __device__ __forceinline__ double bmin(double v, double* red, int tid)
 {
+    constexpr int NW = NT / 64;
     v = wave_min(v);
     const int lane = tid & 63, wave = tid >> 6;
     __syncthreads();
@@ -119,10 +127,11 @@ __device__ __forceinline__ double bmin(double v, double* red, int tid)
 }
 
 // exclusive prefix of flag over physical positions j = k * NT + tid
-template <int PPT>
+template <int NT, int PPT>
 __device__ __forceinline__ int phys_scan(const bool (&flag)[PPT], int (&pre)[PPT], uint32_t* wtot,
                                          int tid)
 {
+    constexpr int NW = NT / 64;
     const int lane = tid & 63, wave = tid >> 6;
     int wpre[PPT];
     __syncthreads();
@@ -195,16 +204,16 @@ __device__ __forceinline__ int fate(const Parts<real, DIM, PPT>& P, int k)
 // moments of the live particles (fate keep or reassigned): centred (two
 // passes) and raw sums; E = sum w |c|^2 / 2.  Every thread gets the results.
 // ---------------------------------------------------------------------------
-template <typename real, int DIM, int PPT>
-__device__ void moments_r(const Parts<real, DIM, PPT>& P, const Lds& L, int tid, double* cen,
-                          double* raw, double* E)
+template <int NT, typename real, int DIM, int PPT>
+__device__ void moments_r(const Parts<real, DIM, PPT>& P, const Lds& L, int tid, int nuse,
+                          double* cen, double* raw, double* E)
 {
     double a[14];
 #pragma unroll
     for (int q = 0; q < 14; ++q) a[q] = 0.0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        if (fate(P, k) <= FT_REASSIGN) {
+        if (k * NT < nuse && fate(P, k) <= FT_REASSIGN) {
             const double w = (double)P.w[k];
             const double c0 = (double)P.c0[k], c1 = (double)P.c1[k], c2 = (double)P.c2[k];
             const double cc = c0 * c0 + c1 * c1 + c2 * c2;
@@ -224,7 +233,7 @@ __device__ void moments_r(const Parts<real, DIM, PPT>& P, const Lds& L, int tid,
             a[13] += w * cc * c2;
         }
     }
-    bsum(a, L.red, tid);
+    bsum<NT>(a, L.red, tid);
     const double s0 = a[0];
     double U[3] = {0.0, 0.0, 0.0};
     if (s0 != 0.0)
@@ -235,7 +244,7 @@ __device__ void moments_r(const Parts<real, DIM, PPT>& P, const Lds& L, int tid,
     for (int q = 0; q < 9; ++q) b[q] = 0.0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        if (fate(P, k) <= FT_REASSIGN) {
+        if (k * NT < nuse && fate(P, k) <= FT_REASSIGN) {
             const double w = (double)P.w[k];
             const double C0 = (double)P.c0[k] - U[0], C1 = (double)P.c1[k] - U[1];
             const double C2 = (double)P.c2[k] - U[2];
@@ -251,7 +260,7 @@ __device__ void moments_r(const Parts<real, DIM, PPT>& P, const Lds& L, int tid,
             b[8] += w * CC * C2;
         }
     }
-    bsum(b, L.red, tid);
+    bsum<NT>(b, L.red, tid);
     cen[0] = s0;
 #pragma unroll
     for (int q = 0; q < 3; ++q) cen[1 + q] = U[q];
@@ -270,10 +279,10 @@ __device__ void moments_r(const Parts<real, DIM, PPT>& P, const Lds& L, int tid,
 // positions [a, a + n) with logical slots [ls, ls + n).  Sampling in double
 // precision, stored once rounded.  Optional zero-moment projection.
 // ---------------------------------------------------------------------------
-template <typename real, int DIM, int PPT>
+template <int NT, typename real, int DIM, int PPT>
 __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L, int batch,
                        int cell, int ix, int iy, uint32_t step, const CellF& f, double pne, int a,
-                       int ls, int tid, uint32_t* errbits, double* marg)
+                       int ls, int tid, uint32_t* errbits, double* marg, bool can_defer)
 {
     if (!f.valid || !(pne > 0.0) || !(f.x > 0.0)) return 0;
     const double m1 = f.x < 1.0 ? f.x : 1.0;
@@ -285,6 +294,8 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
     int na = (int)fl + (u < v - fl ? 1 : 0);
     if (marg) *marg = fmin(*marg, fabs(u - (v - fl)));
     if (ls + na > I.max_ppc || a + na > PPT * NT) {
+        // too many for this shape's slots only: a larger shape redoes the cell
+        if (can_defer && ls + na <= I.max_ppc) return -1;
         *errbits |= ERR_CAPACITY;
         const int room_log = I.max_ppc - ls, room_phys = PPT * NT - a;
         na = room_log < room_phys ? room_log : room_phys;
@@ -297,7 +308,7 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int j = k * NT + tid;
-        if (j >= a && j < a + na) {
+        if (k * NT + NT > a && k * NT < a + na && j >= a && j < a + na) {
             const int q = j - a;
             uint32_t rr[4];
             draw(I, step, PUR_SPAWN_POS, (uint32_t)batch, (uint32_t)cell, (uint32_t)q, rr);
@@ -324,7 +335,7 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int j = k * NT + tid;
-            if (j >= a && j < a + na) {
+            if (k * NT + NT > a && k * NT < a + na && j >= a && j < a + na) {
                 double psi[5];
                 psi5((double)P.c0[k], (double)P.c1[k], (double)P.c2[k], f.U, sq, f.theta, psi);
                 const double w = (double)P.w[k];
@@ -337,58 +348,59 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
                 for (int r1 = 0; r1 < 5; ++r1) g[15 + r1] += w * psi[r1];
             }
         }
-        bsum(g, L.red, tid);
-        double G[5][5], Lc[5][5];
-        {
+        bsum<NT>(g, L.red, tid);
+        // 5x5 Gram solve by one lane in LDS (rolled loops: few registers)
+        double* G = L.sc;       // [25]
+        double* lam = L.sc + 32; // [5], lam[5] = 1 if solvable
+        if (tid == 0) {
             int q = 0;
-#pragma unroll
+#pragma unroll 1
             for (int r1 = 0; r1 < 5; ++r1)
-#pragma unroll
+#pragma unroll 1
                 for (int s1 = 0; s1 <= r1; ++s1) {
-                    G[r1][s1] = g[q];
-                    G[s1][r1] = g[q];
+                    G[r1 * 5 + s1] = g[q];
+                    G[s1 * 5 + r1] = g[q];
                     ++q;
                 }
-        }
-        bool ok = true;
-#pragma unroll
-        for (int i = 0; i < 5; ++i)
-#pragma unroll
-            for (int jj = 0; jj < 5; ++jj) Lc[i][jj] = 0.0;
-#pragma unroll
-        for (int i = 0; i < 5; ++i)
-#pragma unroll
-            for (int jj = 0; jj <= i; ++jj) {
-                double t = G[i][jj];
-#pragma unroll
-                for (int q = 0; q < jj; ++q) t -= Lc[i][q] * Lc[jj][q];
-                if (i == jj) {
-                    ok = ok && (t > 1e-10 * G[0][0]);
-                    Lc[i][i] = sqrt(t > 0.0 ? t : 1.0);
-                } else {
-                    Lc[i][jj] = t / Lc[jj][jj];
+            const double g00 = G[0];
+            bool ok = true;
+            // in-place Cholesky: lower triangle of G becomes L
+#pragma unroll 1
+            for (int i = 0; i < 5; ++i)
+#pragma unroll 1
+                for (int jj = 0; jj <= i; ++jj) {
+                    double t = G[i * 5 + jj];
+#pragma unroll 1
+                    for (int k2 = 0; k2 < jj; ++k2) t -= G[i * 5 + k2] * G[jj * 5 + k2];
+                    if (i == jj) {
+                        ok = ok && (t > 1e-10 * g00);
+                        G[i * 5 + i] = sqrt(t > 0.0 ? t : 1.0);
+                    } else {
+                        G[i * 5 + jj] = t / G[jj * 5 + jj];
+                    }
                 }
-            }
-        if (ok) {
-            double y[5], lam[5];
-#pragma unroll
+#pragma unroll 1
             for (int i = 0; i < 5; ++i) {
                 double t = g[15 + i];
-#pragma unroll
-                for (int q = 0; q < i; ++q) t -= Lc[i][q] * y[q];
-                y[i] = t / Lc[i][i];
+#pragma unroll 1
+                for (int k2 = 0; k2 < i; ++k2) t -= G[i * 5 + k2] * lam[k2];
+                lam[i] = t / G[i * 5 + i];
             }
-#pragma unroll
+#pragma unroll 1
             for (int i = 4; i >= 0; --i) {
-                double t = y[i];
-#pragma unroll
-                for (int q = i + 1; q < 5; ++q) t -= Lc[q][i] * lam[q];
-                lam[i] = t / Lc[i][i];
+                double t = lam[i];
+#pragma unroll 1
+                for (int k2 = i + 1; k2 < 5; ++k2) t -= G[k2 * 5 + i] * lam[k2];
+                lam[i] = t / G[i * 5 + i];
             }
+            lam[5] = ok ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        if (lam[5] != 0.0) {
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const int j = k * NT + tid;
-                if (j >= a && j < a + na) {
+                if (k * NT + NT > a && k * NT < a + na && j >= a && j < a + na) {
                     double psi[5];
                     psi5((double)P.c0[k], (double)P.c1[k], (double)P.c2[k], f.U, sq, f.theta,
                          psi);
@@ -399,6 +411,7 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
                 }
             }
         }
+        __syncthreads();
     }
     return na;
 }
@@ -472,19 +485,20 @@ __device__ __forceinline__ int resample_one(const InstDev& I, int cell, int slot
 
 // k-th smallest (1-based) rank key among the selected particles: 4 passes of
 // an 8-bit LDS histogram, most significant digit first
-template <typename real, int DIM, int PPT>
-__device__ uint32_t kth_key_r(const Parts<real, DIM, PPT>& P, const Lds& L, int kth, int tid)
+template <int NT, typename real, int DIM, int PPT>
+__device__ uint32_t kth_key_r(const Parts<real, DIM, PPT>& P, const Lds& L, int kth, int nuse,
+                              int tid)
 {
     uint32_t prefix = 0;
     int rem = kth;
 #pragma unroll 1
     for (int shift = 24; shift >= 0; shift -= 8) {
-        L.hist[tid] = 0u;
+        for (int b = tid; b < 256; b += NT) L.hist[b] = 0u;
         __syncthreads();
         const uint32_t hmask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
 #pragma unroll
         for (int k = 0; k < PPT; ++k)
-            if (fate(P, k) == FT_SEL && (P.key[k] & hmask) == prefix)
+            if (k * NT < nuse && fate(P, k) == FT_SEL && (P.key[k] & hmask) == prefix)
                 atomicAdd(&L.hist[(P.key[k] >> shift) & 255u], 1u);
         __syncthreads();
         if (tid < 64) {
@@ -529,8 +543,9 @@ __device__ uint32_t kth_key_r(const Parts<real, DIM, PPT>& P, const Lds& L, int 
     return prefix;
 }
 
-template <typename real, int DIM, int PPT>
-__device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char* smem, int tid)
+template <int NT, typename real, int DIM, int PPT>
+__device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char* smem, int tid,
+                               int g, int* tier_out, int tier_len)
 {
     const int* ctl = I.ctl;
     if (ctl[CTL_ERR] != 0) return;
@@ -544,6 +559,15 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
     const bool per_x = I.face_kind[0] == 2, per_y = I.face_kind[2] == 2;
     uint32_t errbits = 0;
     double* dg = I.diag ? I.diag + (size_t)c * NDIAG : nullptr;
+    // hand the cell to the next larger shape (nothing of it written yet)
+    const bool can_defer = tier_out != nullptr;
+    auto defer = [&]() {
+        if (tid == 0) {
+            const int k = atomicAdd(&tier_out[0], 1);
+            if (k < tier_len) tier_out[1 + k] = g;
+            else atomicOr(&I.ctl[CTL_ERR], (int)ERR_CAPACITY);  // lists not cleared
+        }
+    };
     long long tmark = clock64();
     auto mark = [&](int k) {
         if (dg && tid == 0) {
@@ -627,6 +651,15 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
     __syncthreads();
     const int nwin = (int)L.run_pre[nb];
     int n0 = nwin + nfc;
+    if (can_defer && n0 <= I.max_ppc) {
+        // expected particles added in this launch: about n / r_p per batch
+        const int nbat = ((mode & MODE_RELAX) ? 2 : 0) + ((mode & MODE_MOVE) ? 1 : 0);
+        const double est = n0 + nbat * (1.1 * n0 / I.r_p + 8.0);
+        if (n0 > CAP || est > (double)CAP) {
+            defer();
+            return;
+        }
+    }
     if (n0 > I.max_ppc || n0 > CAP) {
         errbits |= ERR_CAPACITY;
         n0 = I.max_ppc < CAP ? I.max_ppc : CAP;
@@ -653,10 +686,11 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
             in[q] = (const real*)I.pc[cur][q];
             fin[q] = (const real*)I.far_pc[cur][q];
         }
+        const int n0u = uni(n0);
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int j = k * NT + tid;
-            if (j < n0) {
+            if (k * NT < n0u && j < n0) {
                 const uint32_t s = L.srcmap[j];
                 const real* const* src = (s & FARBIT) ? fin : in;
                 const size_t e = (size_t)(s & ~FARBIT);
@@ -689,7 +723,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
         }
         {
             double cen[NMOM], rawt[NMOM], E0;
-            moments_r(P, L, tid, cen, rawt, &E0);
+            moments_r<NT>(P, L, tid, uni(n0), cen, rawt, &E0);
             if (tid == 0) {
                 for (int q = 0; q < NMOM; ++q) Ms[q] = cen[q];
                 Ms[26] = E0;
@@ -701,7 +735,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
                     for (int q = 0; q < NMOM; ++q) {
                         double* Ag = I.avgs + (size_t)q * I.ncell + c;
                         A[q] = (ne - 1.0) / ne * *Ag + 1.0 / ne * rawt[q];
-                        *Ag = A[q];
+                        L.pend[13 + q] = A[q];
                     }
                     if (f.valid) {
                         centred_from_raw(A, ma);
@@ -738,18 +772,23 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
             const double Pn = I.pcur[c];
             double mcnt = __builtin_inf();
             // step 4
-            const int n4 = spawn_r(I, P, L, 4, c, ix, iy, step, f, Pn, n0, n0, tid, &errbits,
-                                   &mcnt);
+            const int n4 = spawn_r<NT>(I, P, L, 4, c, ix, iy, step, f, Pn, n0, n0, tid, &errbits,
+                                   &mcnt, can_defer);
+            if (n4 < 0) {
+                defer();
+                return;
+            }
             const int nl = n0 + n4;
             mark(2);
             // step 5
             const double psel = -expm1(-f.x);
             double ss[2] = {0.0, 0.0};
             double msel = __builtin_inf();
+            const int nlu = uni(nl);
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const int j = k * NT + tid;
-                if (j < nl) {
+                if (k * NT < nlu && j < nl) {
                     uint32_t r[4];
                     draw(I, step, PUR_SELECT, 0u, (uint32_t)c, (uint32_t)j, r);
                     const double u = uni_d(r[0], I.prec);
@@ -763,8 +802,8 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
                     }
                 }
             }
-            bsum(ss, L.red, tid);
-            if (dg) msel = bmin(msel, L.red, tid);
+            bsum<NT>(ss, L.red, tid);
+            if (dg) msel = bmin<NT>(msel, L.red, tid);
             const double S = ss[0];
             const int ns = (int)ss[1];
             int nusp = (int)floor(S + 0.5);
@@ -772,10 +811,10 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
             if (nusp > ns) nusp = ns;
             mark(3);
             uint32_t thr = 0;
-            if (nusp > 0 && nusp < ns) thr = kth_key_r(P, L, nusp, tid);
+            if (nusp > 0 && nusp < ns) thr = kth_key_r<NT>(P, L, nusp, nlu, tid);
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
-                if (fate(P, k) == FT_SEL)
+                if (k * NT < nlu && fate(P, k) == FT_SEL)
                     P.st[k] = (P.st[k] & ~0xFFu) |
                               ((nusp == ns || (nusp > 0 && P.key[k] <= thr)) ? FT_REASSIGN
                                                                              : FT_DELETE);
@@ -784,15 +823,19 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
             double fbs[1] = {0.0};
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
-                if (fate(P, k) == FT_REASSIGN) {
+                if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
                     fbs[0] += (double)resample_one(I, c, k * NT + tid, step, f, Pn, P.c0[k],
                                                    P.c1[k], P.c2[k]);
                     P.w[k] = (real)1.0;
                 }
             mark(5);
             // step 7
-            const int n7 = spawn_r(I, P, L, 7, c, ix, iy, step, f, Pn, nl, nl, tid, &errbits,
-                                   &mcnt);
+            const int n7 = spawn_r<NT>(I, P, L, 7, c, ix, iy, step, f, Pn, nl, nl, tid, &errbits,
+                                   &mcnt, can_defer);
+            if (n7 < 0) {
+                defer();
+                return;
+            }
             nphys = nl + n7;
             mark(6);
             // conservation of the cell's mass, momentum and energy
@@ -801,8 +844,10 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
                 double cs[8];
 #pragma unroll
                 for (int q = 0; q < 8; ++q) cs[q] = 0.0;
+                const int npu = uni(nphys);
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
+                    if (k * NT >= npu) continue;
                     const int fk = fate(P, k);
                     const double w = (double)P.w[k];
                     const double c0 = (double)P.c0[k], c1 = (double)P.c1[k];
@@ -819,7 +864,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
                         cs[7] += c2;
                     }
                 }
-                bsum(cs, L.red, tid);
+                bsum<NT>(cs, L.red, tid);
                 if (nusp == 0) {
                     flags |= F_NOUSP;
                 } else {
@@ -839,13 +884,13 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
                         double dd[1] = {0.0};
 #pragma unroll
                         for (int k = 0; k < PPT; ++k)
-                            if (fate(P, k) == FT_REASSIGN) {
+                            if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
                                 const double e0 = (double)P.c0[k] - cb[0];
                                 const double e1 = (double)P.c1[k] - cb[1];
                                 const double e2 = (double)P.c2[k] - cb[2];
                                 dd[0] += e0 * e0 + e1 * e1 + e2 * e2;
                             }
-                        bsum(dd, L.red, tid);
+                        bsum<NT>(dd, L.red, tid);
                         const double D = dd[0];
                         const double a2 = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
                         double sc = 1.0;
@@ -859,7 +904,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
                         }
 #pragma unroll
                         for (int k = 0; k < PPT; ++k)
-                            if (fate(P, k) == FT_REASSIGN) {
+                            if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
                                 P.c0[k] = (real)(a[0] + sc * ((double)P.c0[k] - cb[0]));
                                 P.c1[k] = (real)(a[1] + sc * ((double)P.c1[k] - cb[1]));
                                 P.c2[k] = (real)(a[2] + sc * ((double)P.c2[k] - cb[2]));
@@ -869,7 +914,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
                 }
             }
             double fbt[1] = {fbs[0]};
-            bsum(fbt, L.red, tid);
+            bsum<NT>(fbt, L.red, tid);
             mark(7);
             // logical slots of the survivors (slot order), step-7 particles last
             {
@@ -877,7 +922,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
                 int pre[PPT];
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) alive[k] = fate(P, k) <= FT_REASSIGN;
-                nlog = phys_scan(alive, pre, L.wtot, tid);
+                nlog = phys_scan<NT>(alive, pre, L.wtot, tid);
 #pragma unroll
                 for (int k = 0; k < PPT; ++k)
                     if (alive[k]) P.st[k] = (P.st[k] & 0xFFu) | ((uint32_t)pre[k] << 8);
@@ -903,21 +948,16 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
         // step 8: moments of f^{n+1}, Eq. 34 averages
         {
             double cen1[NMOM], raw1[NMOM], E1;
-            moments_r(P, L, tid, cen1, raw1, &E1);
+            moments_r<NT>(P, L, tid, uni(nphys), cen1, raw1, &E1);
             if (tid == 0) {
-                I.cnt[c] = nlog;
+                L.pend[26] = (double)nlog;
                 const double ne = avg_window(I.n_avg, nsamp);
                 for (int q = 0; q < NMOM; ++q) {
                     Ms[q] = cen1[q];
-                    I.mom[(size_t)q * I.ncell + c] = cen1[q];
-                    I.raw[(size_t)q * I.ncell + c] = raw1[q];
-                    if ((int)step >= I.avg_start) {
-                        double* A = I.avg + (size_t)q * I.ncell + c;
-                        *A = (ne - 1.0) / ne * *A + 1.0 / ne * raw1[q];
-                        Ms[13 + q] = *A;
-                    } else {
-                        Ms[13 + q] = I.avg[(size_t)q * I.ncell + c];
-                    }
+                    L.pend[q] = raw1[q];
+                    const double A = I.avg[(size_t)q * I.ncell + c];
+                    Ms[13 + q] =
+                        (int)step >= I.avg_start ? (ne - 1.0) / ne * A + 1.0 / ne * raw1[q] : A;
                 }
                 if (dg) {
                     dg[D_FLAGS] = flags;
@@ -933,17 +973,31 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
         mark(9);
     } else if (mode & MODE_MOMENTS) {
         double cen1[NMOM], raw1[NMOM], E1;
-        moments_r(P, L, tid, cen1, raw1, &E1);
+        moments_r<NT>(P, L, tid, uni(nphys), cen1, raw1, &E1);
         if (tid == 0) {
-            I.cnt[c] = nlog;
+            L.pend[26] = (double)nlog;
             for (int q = 0; q < NMOM; ++q) {
                 Ms[q] = cen1[q];
-                I.mom[(size_t)q * I.ncell + c] = cen1[q];
-                I.raw[(size_t)q * I.ncell + c] = raw1[q];
+                L.pend[q] = raw1[q];
                 Ms[13 + q] = I.avg[(size_t)q * I.ncell + c];
             }
         }
     }
+    // the cell's moments (and J-moment averages) go to HBM only once no
+    // larger shape can take the cell over
+    auto commit = [&]() {
+        if (tid != 0) return;
+        if (mode & (MODE_RELAX | MODE_MOMENTS)) {
+            I.cnt[c] = (int)L.pend[26];
+            for (int q = 0; q < NMOM; ++q) {
+                I.mom[(size_t)q * I.ncell + c] = Ms[q];
+                I.raw[(size_t)q * I.ncell + c] = L.pend[q];
+                I.avg[(size_t)q * I.ncell + c] = Ms[13 + q];
+            }
+        }
+        if ((mode & MODE_RELAX) && I.jmom_mode == 1 && (int)step >= I.avg_start)
+            for (int q = 0; q < NMOM; ++q) I.avgs[(size_t)q * I.ncell + c] = L.pend[13 + q];
+    };
 
     real* out[6];
 #pragma unroll
@@ -978,25 +1032,35 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
         const double P2 = (mode & MODE_RELAX) ? I.pcur[c] : I.pprev[c];
         double mc2 = __builtin_inf();
         // step 2 of the next time level
-        const int n2 = spawn_r(I, P, L, 2, c, ix, iy, mstep, f, P2, nphys, nlog, tid, &errbits,
-                               &mc2);
+        const int n2 = spawn_r<NT>(I, P, L, 2, c, ix, iy, mstep, f, P2, nphys, nlog, tid, &errbits,
+                               &mc2, can_defer);
+        if (n2 < 0) {
+            defer();
+            return;
+        }
+        commit();
         nphys += n2;
         nlog += n2;
         mark(10);
         // step 3: advect, walls, destination bin (or far list)
         int clamps = 0;
+        const int npu2 = uni(nphys);
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             uint32_t b = FAR_BIN;
-            if (fate(P, k) <= FT_REASSIGN) {
+            if (k * NT < npu2 && fate(P, k) <= FT_REASSIGN) {
                 real px = DIM == 2 ? P.x[k] : (real)0;
                 real py = P.y[k];
+                real v0 = P.c0[k], v1 = P.c1[k], v2 = P.c2[k];
                 const int slot = (int)(P.st[k] >> 8);
-                const int d = advect<real, DIM>(I, px, py, P.c0[k], P.c1[k], P.c2[k], c, slot,
-                                                mstep, &clamps);
+                const int d = advect<real, DIM>(I, px, py, v0, v1, v2, c, slot, mstep, &clamps);
                 if (DIM == 2) P.x[k] = px;
                 P.y[k] = py;
-                const int dx_ = d % I.nx, dy_ = d / I.nx;
+                P.c0[k] = v0;
+                P.c1[k] = v1;
+                P.c2[k] = v2;
+                const int dy_ = DIM == 2 ? d / I.nx : d;
+                const int dx_ = DIM == 2 ? d - dy_ * I.nx : 0;
                 const int oy = min_image(iy - dy_, I.ny, per_y);
                 const int ox = DIM == 2 ? min_image(ix - dx_, I.nx, per_x) : 0;
                 if (oy < -I.Ky || oy > I.Ky || ox < -I.Kx || ox > I.Kx) {
@@ -1083,7 +1147,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
         mark(13);
         if (dg) {
             double cl[1] = {(double)clamps};
-            bsum(cl, L.red, tid);
+            bsum<NT>(cl, L.red, tid);
             if (tid == 0) {
                 dg[D_N2] = n2;
                 dg[D_CLAMP] = cl[0];
@@ -1091,6 +1155,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
             }
         }
     } else {
+        commit();
         // stay layout: every live particle at its logical slot of its own cell
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -1108,6 +1173,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
         for (int b = tid; b <= nb; b += NT) tout[b] = b <= centre ? 0u : (uint32_t)nlog;
     }
     if (nlog > I.max_ppc || nphys > CAP) errbits |= ERR_CAPACITY;
+    if (dg && tid == 0) dg[D_SHAPE_SLOTS] = (double)CAP;
     const uint64_t em = __ballot(errbits != 0);
     if (em) {
         uint32_t e = errbits;
@@ -1117,39 +1183,40 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
     }
 }
 
-template <typename real, int DIM, int PPT>
-__global__ void __launch_bounds__(NT, 2) cell_kernel(Batch B)
+template <typename real, int DIM, int NT, int PPT>
+__global__ void __launch_bounds__(NT) cell_kernel(Batch B)
 {
+    // one workgroup per cell (no loop over cells: a loop would let the
+    // compiler hoist constants across the whole cell body)
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
-    for (int g = blockIdx.x; g < B.ncells; g += gridDim.x) {
-        int lo = 0, hi = B.ninst - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (B.base[mid] <= g) lo = mid;
-            else hi = mid - 1;
-        }
-        process_cell_r<real, DIM, PPT>(B.inst[lo], g - B.base[lo], B.mode, smem, tid);
-        __syncthreads();
+    int g = blockIdx.x;
+    if (B.tier_in) {
+        // cells left over by the next smaller shape
+        if (g >= B.tier_in[0]) return;
+        g = B.tier_in[1 + g];
     }
+    if (g >= B.ncells) return;
+    int lo = 0, hi = B.ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (B.base[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    process_cell_r<NT, real, DIM, PPT>(B.inst[lo], g - B.base[lo], B.mode, smem, tid, g,
+                                       B.tier_out, B.ncells);
 }
 
-#define USP_CELL_INST(R, D, PPT) template __global__ void cell_kernel<R, D, PPT>(Batch);
-USP_CELL_INST(float, 1, 1)
-USP_CELL_INST(float, 1, 2)
-USP_CELL_INST(float, 1, 4)
-USP_CELL_INST(float, 1, 8)
-USP_CELL_INST(float, 2, 1)
-USP_CELL_INST(float, 2, 2)
-USP_CELL_INST(float, 2, 4)
-USP_CELL_INST(float, 2, 8)
-USP_CELL_INST(double, 1, 1)
-USP_CELL_INST(double, 1, 2)
-USP_CELL_INST(double, 1, 4)
-USP_CELL_INST(double, 1, 8)
-USP_CELL_INST(double, 2, 1)
-USP_CELL_INST(double, 2, 2)
-USP_CELL_INST(double, 2, 4)
-USP_CELL_INST(double, 2, 8)
+#define USP_CELL_INST(R, D, NT, PPT) template __global__ void cell_kernel<R, D, NT, PPT>(Batch);
+#define USP_CELL_ALL(R, D)       \
+    USP_CELL_INST(R, D, 256, 1)  \
+    USP_CELL_INST(R, D, 256, 2)  \
+    USP_CELL_INST(R, D, 256, 4)  \
+    USP_CELL_INST(R, D, 256, 6)  \
+    USP_CELL_INST(R, D, 512, 4)
+USP_CELL_ALL(float, 1)
+USP_CELL_ALL(float, 2)
+USP_CELL_ALL(double, 1)
+USP_CELL_ALL(double, 2)
 
 }  // namespace usp

@@ -44,6 +44,8 @@ enum {
     D_MARG_SEL, D_MARG_ROUND, D_MARG_CNT, D_WR, D_S2, D_MARG_CNT2
 };
 enum { F_SKIP = 1, F_FAILMASS = 2, F_FAILENERGY = 4, F_NOUSP = 8 };
+// device-only diagnostic slot: particle slots of the shape that finished the cell
+constexpr int D_SHAPE_SLOTS = 47;
 
 // Everything a kernel needs to know about one solver instance.  Lives in
 // device memory; read-only during a launch.
@@ -90,6 +92,12 @@ struct Batch {
     int ninst;
     int ncells;           // total cells
     int mode;
+    // per-cell shape tiers: a launch of a small shape hands cells that need
+    // more particle slots to the next shape.  Each list is [count, cells...].
+    int* tiers = nullptr;           // NSHAPE lists of tier_stride ints (counts cleared by ctl_kernel)
+    int tier_stride = 0;
+    const int* tier_in = nullptr;   // cells of this launch (null: every cell)
+    int* tier_out = nullptr;        // cells handed on (null: last shape, overflow is an error)
 };
 
 // LDS bytes of the cell kernel for `cap` particle slots and `nb` bins (the
@@ -101,23 +109,34 @@ inline size_t lds_bytes(int cap, int nb)
     b += r16((size_t)cap * 4);                  // gather map
     b += r16((size_t)(cap / 64) * nb * 2);      // bin tile counts
     b += r16(256 * 4) + r16(64 * 4);            // histogram, scan totals
-    b += r16(4 * 24 * 8);                       // reductions
+    b += r16(8 * 24 * 8);                       // reductions (up to 8 waves)
     b += 4 * r16((size_t)(nb + 1) * 4);         // runs, bin offsets
     b += r16((size_t)FAR_LDS * 8) + 3 * r16((size_t)FAR_LDS * 4) + r16(16);  // far arrivals
     b += r16(64 * 8);                           // scalars
+    b += r16(32 * 8);                           // pending moments
     b += r16(256) + r16(32 * 8);                // cell scalars, moments
     return b;
 }
 
-// particles per thread of the cell kernel for a largest cell of max_ppc
-// particles (256 threads; room for the step-2 particles of a full cell)
-inline int pick_ppt(int max_ppc)
+// launch shape of the cell kernel (threads per cell, particle slots per
+// thread) for a largest cell of max_ppc particles, with room for the step-2
+// particles of a full cell.  At most 6 slots per thread: more spill registers.
+// Slot columns beyond a cell's count are skipped at run time, so a larger
+// shape costs registers and LDS, not instructions.
+struct Shape {
+    int nt, ppt;
+};
+constexpr int NSHAPE = 5;
+constexpr Shape SHAPES[NSHAPE] = {{256, 1}, {256, 2}, {256, 4}, {256, 6}, {512, 4}};
+inline int pick_shape_index(int max_ppc)
 {
     const int need = max_ppc + max_ppc / 8 + 1;
-    if (need <= 256) return 1;
-    if (need <= 512) return 2;
-    if (need <= 1024) return 4;
-    return 8;
+    for (int i = 0; i + 1 < NSHAPE; ++i)
+        if (need <= SHAPES[i].nt * SHAPES[i].ppt) return i;
+    return NSHAPE - 1;
 }
+inline Shape pick_shape(int max_ppc) { return SHAPES[pick_shape_index(max_ppc)]; }
+// the first shape a cell is tried with when its instance needs a larger one
+constexpr int TIER_FIRST = 2;
 
 }  // namespace usp

@@ -302,12 +302,20 @@ __device__ __forceinline__ void psi5(double c0, double c1, double c2, const doub
 // ---------------------------------------------------------------------------
 // Wall-to-wall trace of a particle that leaves the domain during the step
 // (double precision); rare, so kept out of line.
+template <typename real>
+struct Flight {
+    real px, py, c0, c1, c2;
+    int clamped;
+};
+
+// Values in, values out: no address of the caller's registers escapes.
 template <typename real, int DIM>
-__device__ __noinline__ void wall_trace(const InstDev& I, real& px, real& py, real& c0, real& c1,
-                                        real& c2, int src_cell, int slot, uint32_t step,
-                                        int* clamp)
+__device__ __noinline__ Flight<real> wall_trace(const InstDev& I, real px, real py, real c0,
+                                                real c1, real c2, int src_cell, int slot,
+                                                uint32_t step)
 {
     const double lo[2] = {I.x0, I.y0}, hi[2] = {I.x1, I.y1};
+    int clamped = 0;
     {
         double pos[2] = {(double)px, (double)py};
         double vel[3] = {(double)c0, (double)c1, (double)c2};
@@ -319,7 +327,7 @@ __device__ __noinline__ void wall_trace(const InstDev& I, real& px, real& py, re
                     if (pos[a] < lo[a]) pos[a] = lo[a];
                     if (pos[a] > hi[a]) pos[a] = hi[a];
                 }
-                ++*clamp;
+                ++clamped;
                 break;
             }
             double te = __builtin_inf();
@@ -381,6 +389,14 @@ __device__ __noinline__ void wall_trace(const InstDev& I, real& px, real& py, re
         c1 = (real)vel[1];
         c2 = (real)vel[2];
     }
+    Flight<real> fo;
+    fo.px = px;
+    fo.py = py;
+    fo.c0 = c0;
+    fo.c1 = c1;
+    fo.c2 = c2;
+    fo.clamped = clamped;
+    return fo;
 }
 
 template <typename real, int DIM>
@@ -397,7 +413,13 @@ __device__ __forceinline__ int advect(const InstDev& I, real& px, real& py, real
         px = np0;
         py = np1;
     } else {
-        wall_trace<real, DIM>(I, px, py, c0, c1, c2, src_cell, slot, step, clamp);
+        const Flight<real> fl = wall_trace<real, DIM>(I, px, py, c0, c1, c2, src_cell, slot, step);
+        px = fl.px;
+        py = fl.py;
+        c0 = fl.c0;
+        c1 = fl.c1;
+        c2 = fl.c2;
+        *clamp += fl.clamped;
     }
     if (I.accel[0] != 0.0) c0 = c0 + (real)(I.accel[0] * I.dt);
     if (I.accel[1] != 0.0) c1 = c1 + (real)(I.accel[1] * I.dt);

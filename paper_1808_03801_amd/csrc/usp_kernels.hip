@@ -119,6 +119,8 @@ __global__ void fields_kernel(Batch B, int init)
 __global__ void ctl_kernel(Batch B, int relaxed)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && B.tiers)
+        for (int t = 0; t < NSHAPE; ++t) B.tiers[(size_t)t * B.tier_stride] = 0;
     if (i >= B.ninst) return;
     int* ctl = B.inst[i].ctl;
     if (ctl[CTL_ERR] != 0) return;

@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -20,7 +21,7 @@
 #include "usp_common.h"
 
 namespace usp {
-template <typename real, int DIM, int PPT>
+template <typename real, int DIM, int NT, int PPT>
 __global__ void cell_kernel(Batch B);
 template <typename real, int DIM>
 __global__ void init_kernel(Batch B, const double* init_n, const double* init_u,
@@ -58,11 +59,16 @@ struct usp_ctx {
     // kernel timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-    // batch descriptor cache
-    std::vector<int> last_ids;
-    InstDev* bd = nullptr;
-    int* bbase = nullptr;
-    int bcap = 0;
+    // device descriptor tables of launch groups, keyed by their instance ids
+    struct Group {
+        InstDev* d = nullptr;
+        int* base = nullptr;
+        size_t bytes = 0;
+    };
+    std::map<std::vector<int>, Group> groups;
+    // lists of the per-cell shape tiers (NSHAPE x (1 + tier_cells) ints)
+    int* tiers = nullptr;
+    int tier_cells = 0;
 };
 
 namespace {
@@ -198,39 +204,76 @@ usp_status with_kernel(int prec, int dim, F f)
 }
 
 template <typename real, int D>
-const void* cell_kernel_for(int ppt)
+const void* cell_kernel_for(Shape sh)
 {
-    switch (ppt) {
-        case 1: return (const void*)cell_kernel<real, D, 1>;
-        case 2: return (const void*)cell_kernel<real, D, 2>;
-        case 4: return (const void*)cell_kernel<real, D, 4>;
-        default: return (const void*)cell_kernel<real, D, 8>;
+    if (sh.nt == 512) return (const void*)cell_kernel<real, D, 512, 4>;
+    switch (sh.ppt) {
+        case 1: return (const void*)cell_kernel<real, D, 256, 1>;
+        case 2: return (const void*)cell_kernel<real, D, 256, 2>;
+        case 4: return (const void*)cell_kernel<real, D, 256, 4>;
+        default: return (const void*)cell_kernel<real, D, 256, 6>;
     }
 }
 
-usp_status launch_cell(usp_ctx* ctx, const Batch& B, int prec, int dim, int max_nb, int ppt)
+usp_status ensure_tiers(usp_ctx* ctx, int ncells)
 {
-    const size_t lds = lds_bytes(ppt * 256, max_nb);
-    return with_kernel(prec, dim, [&](auto* rp, auto dimc) -> usp_status {
-        using real = std::remove_pointer_t<decltype(rp)>;
-        constexpr int D = decltype(dimc)::value;
-        const void* kern = cell_kernel_for<real, D>(ppt);
-        HIPCHK(ctx, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lds));
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (ctx->timing) {
-            HIPCHK(ctx, hipEventCreate(&e0));
-            HIPCHK(ctx, hipEventCreate(&e1));
-            HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
-        }
-        void* args[] = {(void*)&B};
-        HIPCHK(ctx, hipLaunchKernel(kern, dim3(B.ncells), dim3(256), args, lds, ctx->stream));
-        if (ctx->timing) {
-            HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
-            ctx->events.emplace_back(e0, e1);
-        }
-        return USP_OK;
-    });
+    if (ncells <= ctx->tier_cells) return USP_OK;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->tiers) dfree(ctx, ctx->tiers, sizeof(int) * NSHAPE * (size_t)(1 + ctx->tier_cells));
+    const size_t bytes = sizeof(int) * NSHAPE * (size_t)(1 + ncells);
+    ctx->tiers = (int*)dalloc(ctx, bytes);
+    ctx->tier_cells = 0;
+    if (!ctx->tiers) return fail(ctx, USP_ENOMEM, "shape tier lists");
+    HIPCHK(ctx, hipMemsetAsync(ctx->tiers, 0, bytes, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->tier_cells = ncells;
+    return USP_OK;
+}
+
+void attach_tiers(usp_ctx* ctx, Batch& B)
+{
+    B.tiers = ctx->tiers;
+    B.tier_stride = 1 + ctx->tier_cells;
+}
+
+// one cell-kernel pass over the batch.  Instances that need more particle
+// slots than the 256 x 4 shape run every cell with that shape first; a cell
+// that turns out to need more is handed on, untouched, to the next shape.
+usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int max_nb, int top)
+{
+    usp_status st = ensure_tiers(ctx, B.ncells);
+    if (st) return st;
+    attach_tiers(ctx, B);
+    const int lo = std::min(top, TIER_FIRST);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->timing) {
+        HIPCHK(ctx, hipEventCreate(&e0));
+        HIPCHK(ctx, hipEventCreate(&e1));
+        HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
+    }
+    for (int t = lo; t <= top; ++t) {
+        const Shape sh = SHAPES[t];
+        B.tier_in = t == lo ? nullptr : B.tiers + (size_t)(t - 1) * B.tier_stride;
+        B.tier_out = t == top ? nullptr : B.tiers + (size_t)t * B.tier_stride;
+        const size_t lds = lds_bytes(sh.ppt * sh.nt, max_nb);
+        st = with_kernel(prec, dim, [&](auto* rp, auto dimc) -> usp_status {
+            using real = std::remove_pointer_t<decltype(rp)>;
+            constexpr int D = decltype(dimc)::value;
+            const void* kern = cell_kernel_for<real, D>(sh);
+            HIPCHK(ctx, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)lds));
+            void* args[] = {(void*)&B};
+            HIPCHK(ctx,
+                   hipLaunchKernel(kern, dim3(B.ncells), dim3(sh.nt), args, lds, ctx->stream));
+            return USP_OK;
+        });
+        if (st) return st;
+    }
+    if (ctx->timing) {
+        HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
+        ctx->events.emplace_back(e0, e1);
+    }
+    return USP_OK;
 }
 
 usp_status launch_fields(usp_ctx* ctx, const Batch& B, int init)
@@ -242,8 +285,9 @@ usp_status launch_fields(usp_ctx* ctx, const Batch& B, int init)
     return USP_OK;
 }
 
-usp_status launch_ctl(usp_ctx* ctx, const Batch& B, int relaxed)
+usp_status launch_ctl(usp_ctx* ctx, Batch B, int relaxed)
 {
+    attach_tiers(ctx, B);
     hipLaunchKernelGGL(ctl_kernel, dim3((B.ninst + 63) / 64), dim3(64), 0, ctx->stream, B,
                        relaxed);
     HIPCHK(ctx, hipGetLastError());
@@ -283,11 +327,22 @@ usp_status err_status(usp_ctx* ctx, int e)
     return USP_OK;
 }
 
+void drop_groups(usp_ctx* ctx)
+{
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->groups) {
+        dfree(ctx, kv.second.d, kv.second.bytes);
+        dfree(ctx, kv.second.base, 0);
+    }
+    ctx->groups.clear();
+}
+
 // moments of the current state + P_ne from them (initial / loaded states)
 usp_status finish_state(usp_ctx* ctx, Instance* in)
 {
     Batch B = single_batch(in, MODE_MOMENTS);
-    usp_status s = launch_cell(ctx, B, in->h.prec, in->h.dim, in->h.nb, pick_ppt(in->h.max_ppc));
+    usp_status s = launch_cell(ctx, B, in->h.prec, in->h.dim, in->h.nb,
+                               pick_shape_index(in->h.max_ppc));
     if (s) return s;
     if ((s = launch_fields(ctx, B, 1))) return s;
     return launch_ctl(ctx, B, 0);
@@ -319,8 +374,8 @@ void usp_destroy(usp_ctx* ctx)
     for (size_t i = 0; i < ctx->inst.size(); ++i)
         if (ctx->inst[i] && ctx->inst[i]->alive) usp_instance_free(ctx, (int)i);
     for (Instance* in : ctx->inst) delete in;
-    if (ctx->bd) dfree(ctx, ctx->bd, sizeof(InstDev) * ctx->bcap);
-    if (ctx->bbase) dfree(ctx, ctx->bbase, sizeof(int) * (ctx->bcap + 1));
+    drop_groups(ctx);
+    if (ctx->tiers) dfree(ctx, ctx->tiers, sizeof(int) * NSHAPE * (size_t)(1 + ctx->tier_cells));
     delete ctx;
 }
 
@@ -486,7 +541,7 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
     in->alive = true;
     ctx->inst.push_back(in);
     *id_out = (int)ctx->inst.size() - 1;
-    ctx->last_ids.clear();
+    drop_groups(ctx);
     int ctl[CTL_N];
     if ((s = read_ctl(ctx, in, ctl))) return s;
     return err_status(ctx, ctl[CTL_ERR]);
@@ -501,7 +556,7 @@ usp_status usp_instance_free(usp_ctx* ctx, int id)
     ctx->allocated -= std::min(ctx->allocated, in->bytes);
     in->allocs.clear();
     in->alive = false;
-    ctx->last_ids.clear();
+    drop_groups(ctx);
     return USP_OK;
 }
 
@@ -518,60 +573,59 @@ usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps)
 {
     if (!ctx || !ids || n_ids <= 0) return fail(ctx, USP_EINVAL, "no instances");
     if (nsteps <= 0) return USP_OK;
-    // group the instances by kernel flavour (precision, dimension)
-    for (int g = 0; g < 4; ++g) {
-        const int prec = g < 2 ? 32 : 64, dim = (g & 1) ? 2 : 1;
+    // group the instances by kernel flavour (precision, dimension, shape)
+    for (int i = 0; i < n_ids; ++i)
+        if (!get_inst(ctx, ids[i])) return fail(ctx, USP_ESTATE, "unknown or freed instance in step");
+    for (int g = 0; g < 4 * NSHAPE; ++g) {
+        const int prec = (g & 1) ? 64 : 32, dim = (g & 2) ? 2 : 1;
         std::vector<int> sel;
         for (int i = 0; i < n_ids; ++i) {
             Instance* in = get_inst(ctx, ids[i]);
-            if (!in) return fail(ctx, USP_ESTATE, "unknown or freed instance in step");
-            if (in->h.prec == prec && in->h.dim == dim) sel.push_back(ids[i]);
+            if (in->h.prec == prec && in->h.dim == dim &&
+                pick_shape_index(in->h.max_ppc) == (g >> 2))
+                sel.push_back(ids[i]);
         }
         if (sel.empty()) continue;
-        // descriptor array of this group (cached while the group is unchanged)
+        // device descriptor table of this group (kept while the group exists)
         std::vector<int> key = sel;
         key.push_back(-1 - g);
-        if (key != ctx->last_ids) {
-            if ((int)sel.size() > ctx->bcap) {
-                if (ctx->bd) dfree(ctx, ctx->bd, sizeof(InstDev) * ctx->bcap);
-                if (ctx->bbase) dfree(ctx, ctx->bbase, sizeof(int) * (ctx->bcap + 1));
-                ctx->bcap = std::max((int)sel.size(), 16);
-                ctx->bd = (InstDev*)dalloc(ctx, sizeof(InstDev) * ctx->bcap);
-                ctx->bbase = (int*)dalloc(ctx, sizeof(int) * (ctx->bcap + 1));
-                if (!ctx->bd || !ctx->bbase) return fail(ctx, USP_ENOMEM, "batch table");
-            }
+        auto it = ctx->groups.find(key);
+        if (it == ctx->groups.end()) {
+            usp_ctx::Group G;
+            G.bytes = sizeof(InstDev) * sel.size();
+            G.d = (InstDev*)dalloc(ctx, G.bytes);
+            G.base = (int*)dalloc(ctx, sizeof(int) * (sel.size() + 1));
+            if (!G.d || !G.base) return fail(ctx, USP_ENOMEM, "batch table");
             std::vector<InstDev> hd;
             std::vector<int> base(1, 0);
             for (int id : sel) {
                 hd.push_back(ctx->inst[id]->h);
                 base.push_back(base.back() + ctx->inst[id]->h.ncell);
             }
-            HIPCHK(ctx, hipMemcpyAsync(ctx->bd, hd.data(), sizeof(InstDev) * hd.size(),
-                                       hipMemcpyHostToDevice, ctx->stream));
-            HIPCHK(ctx, hipMemcpyAsync(ctx->bbase, base.data(), sizeof(int) * base.size(),
+            HIPCHK(ctx, hipMemcpyAsync(G.d, hd.data(), G.bytes, hipMemcpyHostToDevice,
+                                       ctx->stream));
+            HIPCHK(ctx, hipMemcpyAsync(G.base, base.data(), sizeof(int) * base.size(),
                                        hipMemcpyHostToDevice, ctx->stream));
             HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-            ctx->last_ids = key;
+            it = ctx->groups.emplace(key, G).first;
         }
         Batch B;
-        B.inst = ctx->bd;
-        B.base = ctx->bbase;
+        B.inst = it->second.d;
+        B.base = it->second.base;
         B.ninst = (int)sel.size();
         B.ncells = 0;
-        int max_nb = 0, max_ppc = 0;
+        int max_nb = 0;
         for (int id : sel) {
             B.ncells += ctx->inst[id]->h.ncell;
-            max_ppc = std::max(max_ppc, ctx->inst[id]->h.max_ppc);
             max_nb = std::max(max_nb, ctx->inst[id]->h.nb);
         }
-        const int ppt = pick_ppt(max_ppc);
         usp_status s;
         B.mode = MODE_MOVE;
-        if ((s = launch_cell(ctx, B, prec, dim, max_nb, ppt))) return s;
+        if ((s = launch_cell(ctx, B, prec, dim, max_nb, g >> 2))) return s;
         if ((s = launch_ctl(ctx, B, 0))) return s;
         for (int k = 0; k < nsteps; ++k) {
             B.mode = k + 1 < nsteps ? (MODE_RELAX | MODE_MOVE) : MODE_RELAX;
-            if ((s = launch_cell(ctx, B, prec, dim, max_nb, ppt))) return s;
+            if ((s = launch_cell(ctx, B, prec, dim, max_nb, g >> 2))) return s;
             if ((s = launch_fields(ctx, B, 0))) return s;
             if ((s = launch_ctl(ctx, B, 1))) return s;
         }
@@ -774,7 +828,7 @@ usp_status usp_set_diag(usp_ctx* ctx, int id, int on)
     } else if (!on) {
         in->h.diag = nullptr;
     }
-    ctx->last_ids.clear();
+    drop_groups(ctx);
     return upload_desc(ctx, in);
 }
 

@@ -64,6 +64,9 @@ def _cases():
         "cavity_fp32_far": lambda: _window(P.cavity_2d(Kn=0.01, n=16, ppc=80, seed=11), 1),
         "box_fp64_far": lambda: _window(P.homogeneous_box(ncell=15, ppc=300, nu_dt=2.0, pne=0.7,
                                                           precision=64, seed=12), 1),
+        # left state of ~1000 particles per cell: those cells are handed from
+        # the 256 x 4 shape to the larger ones, the right state is not
+        "sod_fp32_tiers": lambda: P.sod_1d(ncell=64, mean_ppc=560, seed=13),
     }
 
 
@@ -117,16 +120,42 @@ def test_single_step_parity(ctx, name):
     o = O.Oracle(pb)
     o.set_state(st)
     g = ctx.add(pb)
-    g.set_diag(True)
-    g.set_state(st)
-    o.step(1)
-    g.step(1)
-    ctx.sync()
-    rep = {}
-    compare_step(pb, o.get_state(), g.get_state(), o.diag(), g.diag(), o.fields(0),
-                 g.fields(0), report=rep)
-    print(name, rep)
-    g.free()
+    try:
+        g.set_diag(True)
+        g.set_state(st)
+        o.step(1)
+        g.step(1)
+        ctx.sync()
+        rep = {}
+        compare_step(pb, o.get_state(), g.get_state(), o.diag(), g.diag(), o.fields(0),
+                     g.fields(0), report=rep)
+        print(name, rep)
+    finally:
+        g.free()
+
+
+@pytest.mark.gpu
+def test_cells_handed_to_larger_shapes():
+    """cells whose particles outgrow the 256 x 4 shape's slots finish in a
+    larger one (parity with the oracle is checked by the single-step test of
+    the same case); here: both kinds of cell occur, split by their count"""
+    usp = _gpu()
+    pb = _cases()["sod_fp32_tiers"]()
+    st = _oracle_state(pb, 3)
+    c = usp.Context(0)
+    try:
+        g = c.add(pb)
+        g.set_diag(True)
+        g.set_state(st)
+        g.step(1)
+        c.sync()
+        slots = g.diag()[:, 47]
+        n_in = g.diag()[:, 0]
+        assert set(np.unique(slots)) <= {1024.0, 1536.0, 2048.0}
+        assert (slots == 1024.0).any() and (slots > 1024.0).any(), np.unique(slots)
+        assert n_in[slots > 1024.0].min() > n_in[slots == 1024.0].max() * 0.9
+    finally:
+        c.close()
 
 
 @pytest.mark.gpu
