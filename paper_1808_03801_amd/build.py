@@ -16,14 +16,37 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
          "-I", os.path.join(HERE, "..", "include")]
 
 
+SOURCES = ("usp_cell_f32_1d.hip", "usp_cell_f32_2d.hip", "usp_cell_f64_1d.hip",
+           "usp_cell_f64_2d.hip", "usp_kernels.hip", "usp_runtime.hip")
+
+
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, f) for f in ("usp_cell.hip", "usp_kernels.hip", "usp_runtime.hip")]
-    cmd = ["hipcc", *FLAGS, *srcs, "-o", LIB + ".tmp"]
+    """compile every source to an object (in parallel), then link the library"""
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    cflags = [f for f in FLAGS if f not in ("-shared",)]
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        cmd = ["hipcc", *cflags, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                  stderr=subprocess.STDOUT, text=True)))
+    errors = []
+    for src, obj, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            errors.append(f"{src}:\n{out}")
+    if errors:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errors))
+    cmd = ["hipcc", "-shared", f"--offload-arch={ARCH}", *[o for _, o, _ in procs],
+           "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
+        raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -22,6 +22,8 @@
 // fate marks them dead, and the logical slot of each survivor comes from a
 // scan.  Physical order is monotone in logical order, so stable ranks taken
 // over physical positions equal those over logical slots.
+#pragma once
+
 #include "usp_device.h"
 
 namespace usp {
@@ -53,6 +55,8 @@ struct Lds {
     double* mom;   // [0..12] centred, [13..25] averages, [26] energy, [27..29] momentum
     double* pend;  // [0..12] raw sums, [13..25] J-moment averages, [26] count: stored
                    // to HBM once the cell can no longer be handed to a larger shape
+    double* pre;   // per-cell inputs loaded at the start: [0..12] J-moment averages,
+                   // [13..25] Eq. 34 averages, [26..38] moments, [39] P_ne^n, [40] P_ne^n-1
 };
 
 static_assert(sizeof(CellF) <= 256, "cell scalars must fit their LDS slot");
@@ -84,6 +88,7 @@ __device__ __forceinline__ Lds carve(unsigned char* sm, int cap, int nb)
     L.f = (CellF*)take(sizeof(CellF));
     L.mom = (double*)take(32 * 8);
     L.pend = (double*)take(32 * 8);
+    L.pre = (double*)take(48 * 8);
     return L;
 }
 
@@ -349,54 +354,48 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
             }
         }
         bsum<NT>(g, L.red, tid);
-        // 5x5 Gram solve by one lane in LDS (rolled loops: few registers)
-        double* G = L.sc;       // [25]
-        double* lam = L.sc + 32; // [5], lam[5] = 1 if solvable
-        if (tid == 0) {
+        // 5x5 Gram solve, unrolled in registers (the same values in every
+        // lane): Cholesky G = L L^T, then L y = b and L^T lam = y
+        double Lm[5][5];
+        {
             int q = 0;
-#pragma unroll 1
+#pragma unroll
             for (int r1 = 0; r1 < 5; ++r1)
-#pragma unroll 1
-                for (int s1 = 0; s1 <= r1; ++s1) {
-                    G[r1 * 5 + s1] = g[q];
-                    G[s1 * 5 + r1] = g[q];
-                    ++q;
-                }
-            const double g00 = G[0];
-            bool ok = true;
-            // in-place Cholesky: lower triangle of G becomes L
-#pragma unroll 1
-            for (int i = 0; i < 5; ++i)
-#pragma unroll 1
-                for (int jj = 0; jj <= i; ++jj) {
-                    double t = G[i * 5 + jj];
-#pragma unroll 1
-                    for (int k2 = 0; k2 < jj; ++k2) t -= G[i * 5 + k2] * G[jj * 5 + k2];
-                    if (i == jj) {
-                        ok = ok && (t > 1e-10 * g00);
-                        G[i * 5 + i] = sqrt(t > 0.0 ? t : 1.0);
-                    } else {
-                        G[i * 5 + jj] = t / G[jj * 5 + jj];
-                    }
-                }
-#pragma unroll 1
-            for (int i = 0; i < 5; ++i) {
-                double t = g[15 + i];
-#pragma unroll 1
-                for (int k2 = 0; k2 < i; ++k2) t -= G[i * 5 + k2] * lam[k2];
-                lam[i] = t / G[i * 5 + i];
-            }
-#pragma unroll 1
-            for (int i = 4; i >= 0; --i) {
-                double t = lam[i];
-#pragma unroll 1
-                for (int k2 = i + 1; k2 < 5; ++k2) t -= G[k2 * 5 + i] * lam[k2];
-                lam[i] = t / G[i * 5 + i];
-            }
-            lam[5] = ok ? 1.0 : 0.0;
+#pragma unroll
+                for (int s1 = 0; s1 <= r1; ++s1) Lm[r1][s1] = g[q++];
         }
-        __syncthreads();
-        if (lam[5] != 0.0) {
+        const double g00 = Lm[0][0];
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+#pragma unroll
+            for (int jj = 0; jj <= i; ++jj) {
+                double t = Lm[i][jj];
+#pragma unroll
+                for (int k2 = 0; k2 < jj; ++k2) t -= Lm[i][k2] * Lm[jj][k2];
+                if (i == jj) {
+                    ok = ok && (t > 1e-10 * g00);
+                    Lm[i][i] = sqrt(t > 0.0 ? t : 1.0);
+                } else {
+                    Lm[i][jj] = t / Lm[jj][jj];
+                }
+            }
+        double lam[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            double t = g[15 + i];
+#pragma unroll
+            for (int k2 = 0; k2 < i; ++k2) t -= Lm[i][k2] * lam[k2];
+            lam[i] = t / Lm[i][i];
+        }
+#pragma unroll
+        for (int i = 4; i >= 0; --i) {
+            double t = lam[i];
+#pragma unroll
+            for (int k2 = i + 1; k2 < 5; ++k2) t -= Lm[k2][i] * lam[k2];
+            lam[i] = t / Lm[i][i];
+        }
+        if (ok) {
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const int j = k * NT + tid;
@@ -411,7 +410,6 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
                 }
             }
         }
-        __syncthreads();
     }
     return na;
 }
@@ -543,6 +541,51 @@ __device__ uint32_t kth_key_r(const Parts<real, DIM, PPT>& P, const Lds& L, int 
     return prefix;
 }
 
+// Cell scalars, computed by wave 0: lane 0 derives f from the centred
+// moments m0 of n particles while lane 1 derives from the centred form of the
+// averaged raw sums A (the same code on two lanes at once).  With use_avg, s
+// and h of the result come from the averages (zero when those are
+// degenerate).  Every lane of wave 0 returns the same values.
+__device__ __forceinline__ CellF pair_derive(const InstDev& I, const double (&m0)[NMOM], int n,
+                                             const double (&A)[NMOM], bool use_avg, int lane)
+{
+    double m[NMOM];
+    if (lane == 1 && use_avg) {
+        centred_from_raw(A, m);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NMOM; ++q) m[q] = m0[q];
+    }
+    CellF fl;
+    derive(I, m, lane == 1 ? 2 : n, fl);
+    CellF f;
+    f.valid = __builtin_amdgcn_readlane(fl.valid, 0);
+    f.S0 = readlane_d(fl.S0, 0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) f.U[q] = readlane_d(fl.U[q], 0);
+    f.trK = readlane_d(fl.trK, 0);
+    f.theta = readlane_d(fl.theta, 0);
+    f.rho = readlane_d(fl.rho, 0);
+    f.p = readlane_d(fl.p, 0);
+    f.T = readlane_d(fl.T, 0);
+    f.mu = readlane_d(fl.mu, 0);
+    f.nu = readlane_d(fl.nu, 0);
+    f.x = readlane_d(fl.x, 0);
+    const bool avg = use_avg && f.valid;
+    const int va = __builtin_amdgcn_readlane(fl.valid, 1);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const double s0 = readlane_d(fl.s[q], 0), s1 = readlane_d(fl.s[q], 1);
+        f.s[q] = avg ? (va ? s1 : 0.0) : s0;
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double h0 = readlane_d(fl.h[q], 0), h1 = readlane_d(fl.h[q], 1);
+        f.h[q] = avg ? (va ? h1 : 0.0) : h0;
+    }
+    return f;
+}
+
 template <int NT, typename real, int DIM, int PPT>
 __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char* smem, int tid,
                                int g, int* tier_out, int tier_len)
@@ -577,6 +620,21 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
         }
     };
     Parts<real, DIM, PPT> P;
+
+    // per-cell inputs of the lane-0 sections, loaded while the gather runs
+    if (tid < 41) {
+        double v = 0.0;
+        if (tid < 13) {
+            if (I.jmom_mode == 1) v = I.avgs[(size_t)tid * I.ncell + c];
+        } else if (tid < 26) {
+            v = I.avg[(size_t)(tid - 13) * I.ncell + c];
+        } else if (tid < 39) {
+            v = I.mom[(size_t)(tid - 26) * I.ncell + c];
+        } else {
+            v = tid == 39 ? I.pcur[c] : I.pprev[c];
+        }
+        L.pre[tid] = v;
+    }
 
     // ---- gather: window bins of the neighbours, then far arrivals
     {
@@ -724,34 +782,31 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
         {
             double cen[NMOM], rawt[NMOM], E0;
             moments_r<NT>(P, L, tid, uni(n0), cen, rawt, &E0);
-            if (tid == 0) {
-                for (int q = 0; q < NMOM; ++q) Ms[q] = cen[q];
-                Ms[26] = E0;
-                for (int q = 0; q < 3; ++q) Ms[27 + q] = rawt[1 + q];
-                derive(I, cen, n0, f);
-                if (I.jmom_mode == 1 && (int)step >= I.avg_start) {
-                    const double ne = avg_window(I.n_avg, nsamp);
-                    double A[NMOM], ma[NMOM];
-                    for (int q = 0; q < NMOM; ++q) {
-                        double* Ag = I.avgs + (size_t)q * I.ncell + c;
-                        A[q] = (ne - 1.0) / ne * *Ag + 1.0 / ne * rawt[q];
-                        L.pend[13 + q] = A[q];
-                    }
-                    if (f.valid) {
-                        centred_from_raw(A, ma);
-                        CellF fa;
-                        derive(I, ma, 2, fa);
-                        for (int q = 0; q < 6; ++q) f.s[q] = fa.valid ? fa.s[q] : 0.0;
-                        for (int q = 0; q < 3; ++q) f.h[q] = fa.valid ? fa.h[q] : 0.0;
-                    }
-                }
-                if (f.valid) {
+            if (tid < 64) {
+                const bool use_avg = I.jmom_mode == 1 && (int)step >= I.avg_start;
+                double A[NMOM];
+                const double ne = avg_window(I.n_avg, nsamp);
+#pragma unroll
+                for (int q = 0; q < NMOM; ++q)
+                    A[q] = (ne - 1.0) / ne * L.pre[q] + 1.0 / ne * rawt[q];
+                CellF fw = pair_derive(I, cen, n0, A, use_avg, tid);
+                if (fw.valid) {
                     // Eq. 33 divisors with P_ne^n
-                    const double Pn = I.pcur[c];
-                    const double da = 1.0 + I.dt * f.nu * Pn / 2.0;
-                    const double db = 1.0 + I.dt * f.nu * I.Pr * Pn / 2.0;
-                    for (int q = 0; q < 6; ++q) f.s[q] /= da;
-                    for (int q = 0; q < 3; ++q) f.h[q] /= db;
+                    const double Pn = L.pre[39];
+                    const double da = 1.0 + I.dt * fw.nu * Pn / 2.0;
+                    const double db = 1.0 + I.dt * fw.nu * I.Pr * Pn / 2.0;
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) fw.s[q] /= da;
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) fw.h[q] /= db;
+                }
+                if (tid == 0) {
+                    for (int q = 0; q < NMOM; ++q) Ms[q] = cen[q];
+                    Ms[26] = E0;
+                    for (int q = 0; q < 3; ++q) Ms[27 + q] = rawt[1 + q];
+                    if (use_avg)
+                        for (int q = 0; q < NMOM; ++q) L.pend[13 + q] = A[q];
+                    f = fw;
                 }
             }
             __syncthreads();
@@ -769,7 +824,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
         if (!f.valid) {
             flags |= F_SKIP;
         } else {
-            const double Pn = I.pcur[c];
+            const double Pn = L.pre[39];
             double mcnt = __builtin_inf();
             // step 4
             const int n4 = spawn_r<NT>(I, P, L, 4, c, ix, iy, step, f, Pn, n0, n0, tid, &errbits,
@@ -955,7 +1010,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
                 for (int q = 0; q < NMOM; ++q) {
                     Ms[q] = cen1[q];
                     L.pend[q] = raw1[q];
-                    const double A = I.avg[(size_t)q * I.ncell + c];
+                    const double A = L.pre[13 + q];
                     Ms[13 + q] =
                         (int)step >= I.avg_start ? (ne - 1.0) / ne * A + 1.0 / ne * raw1[q] : A;
                 }
@@ -979,7 +1034,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
             for (int q = 0; q < NMOM; ++q) {
                 Ms[q] = cen1[q];
                 L.pend[q] = raw1[q];
-                Ms[13 + q] = I.avg[(size_t)q * I.ncell + c];
+                Ms[13 + q] = L.pre[13 + q];
             }
         }
     }
@@ -1008,28 +1063,21 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
     if (mode & MODE_MOVE) {
         const uint32_t mstep = (mode & MODE_RELAX) ? step + 1 : step;
         // cell scalars of f^{n+1} (or f^n when no relaxation ran) for step 2
-        if (tid == 0) {
+        if (tid < 64) {
+            const bool have = (mode & (MODE_RELAX | MODE_MOMENTS)) != 0;
             double m[NMOM], A[NMOM];
+#pragma unroll
             for (int q = 0; q < NMOM; ++q) {
-                m[q] = (mode & (MODE_RELAX | MODE_MOMENTS)) ? Ms[q]
-                                                           : I.mom[(size_t)q * I.ncell + c];
-                A[q] = (mode & (MODE_RELAX | MODE_MOMENTS)) ? Ms[13 + q]
-                                                           : I.avg[(size_t)q * I.ncell + c];
+                m[q] = have ? Ms[q] : L.pre[26 + q];
+                A[q] = have ? Ms[13 + q] : L.pre[13 + q];
             }
-            derive(I, m, nlog, f);
             const int ns_after =
                 nsamp + (((mode & MODE_RELAX) && (int)step >= I.avg_start) ? 1 : 0);
-            if (I.jmom_mode == 1 && ns_after > 0 && f.valid) {
-                double ma[NMOM];
-                centred_from_raw(A, ma);
-                CellF fa;
-                derive(I, ma, 2, fa);
-                for (int q = 0; q < 6; ++q) f.s[q] = fa.valid ? fa.s[q] : 0.0;
-                for (int q = 0; q < 3; ++q) f.h[q] = fa.valid ? fa.h[q] : 0.0;
-            }
+            const CellF fw = pair_derive(I, m, nlog, A, I.jmom_mode == 1 && ns_after > 0, tid);
+            if (tid == 0) f = fw;
         }
         __syncthreads();
-        const double P2 = (mode & MODE_RELAX) ? I.pcur[c] : I.pprev[c];
+        const double P2 = (mode & MODE_RELAX) ? L.pre[39] : L.pre[40];
         double mc2 = __builtin_inf();
         // step 2 of the next time level
         const int n2 = spawn_r<NT>(I, P, L, 2, c, ix, iy, mstep, f, P2, nphys, nlog, tid, &errbits,
@@ -1214,9 +1262,5 @@ __global__ void __launch_bounds__(NT) cell_kernel(Batch B)
     USP_CELL_INST(R, D, 256, 4)  \
     USP_CELL_INST(R, D, 256, 6)  \
     USP_CELL_INST(R, D, 512, 4)
-USP_CELL_ALL(float, 1)
-USP_CELL_ALL(float, 2)
-USP_CELL_ALL(double, 1)
-USP_CELL_ALL(double, 2)
 
 }  // namespace usp

@@ -114,6 +114,7 @@ inline size_t lds_bytes(int cap, int nb)
     b += r16((size_t)FAR_LDS * 8) + 3 * r16((size_t)FAR_LDS * 4) + r16(16);  // far arrivals
     b += r16(64 * 8);                           // scalars
     b += r16(32 * 8);                           // pending moments
+    b += r16(48 * 8);                           // per-cell inputs
     b += r16(256) + r16(32 * 8);                // cell scalars, moments
     return b;
 }
