@@ -13,8 +13,10 @@ region, with all state resident in HBM.
 Prints one JSON line (see the "roofline" and "cpu_baseline" members).
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -25,6 +27,50 @@ PEAK_HBM_GBS = 8000.0
 # algorithmic bytes per particle-step: one read and one write of the particle
 # record (y, cx, cy, cz, w in FP32 = 20 B each way)
 BYTES_PER_PARTICLE_STEP = 40.0
+# algorithmic bytes per cell-step: Eq. 34 averages and J-moment averages read
+# and written (2 x 2 x 13 FP64), moments and raw sums written (2 x 13 FP64),
+# P_ne read (8 B), particle count written (4 B)
+BYTES_PER_CELL_STEP = 6 * 13 * 8 + 8 + 4
+
+# HBM traffic of the cell kernel measured by rocprofv3 (FETCH_SIZE,
+# WRITE_SIZE) on this workload, with the hash of the kernel sources it was
+# measured on: reported only while the sources are unchanged
+PROFILE = os.path.join(ROOT, "profiles", "cell_kernel_thermal_couette_sod_1d.md")
+KERNEL_SOURCES = ("usp_cell_impl.h", "usp_device.h", "usp_common.h", "usp_cell_f32_1d.hip")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1808_03801_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per cell-kernel pass from the committed rocprofv3 summary,
+    or None when it was taken on other kernel sources"""
+    try:
+        txt = open(PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_pass:\s*([0-9.eE+]+)\s+sources:\s*([0-9a-f]+)", txt)
+    if not m or m.group(2) != kernel_source_hash():
+        return None
+    return float(m.group(1))
+
+
+def copy_calibration():
+    """a plain device copy of known size (256 MiB, three times), so that the
+    FETCH_SIZE / WRITE_SIZE counters can be scaled to bytes"""
+    import torch
+    n = 64 * 1024 * 1024
+    a = torch.ones(n, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": n * 4, "copies": 3}), flush=True)
 
 
 def workload():
@@ -61,11 +107,17 @@ def main():
     ap.add_argument("--chunk", type=int, default=20, help="steps per library call")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see the design notes for how the step would shard)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
     from paper_1808_03801_amd import usp
@@ -103,7 +155,8 @@ def main():
     ctx.sync()
     n_roof = sum(i.num_particles() for i in inst)
     avg_ms = ms / max(launches, 1)
-    bytes_per_launch = n_roof * BYTES_PER_PARTICLE_STEP
+    ncells = sum(pb.ncell for pb in pbs)
+    bytes_per_launch = n_roof * BYTES_PER_PARTICLE_STEP + ncells * BYTES_PER_CELL_STEP
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
 
     line = {
@@ -135,7 +188,7 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "avg_launch_ms": avg_ms,
             "bytes_per_launch": bytes_per_launch,
         },

@@ -586,30 +586,47 @@ __device__ __forceinline__ CellF pair_derive(const InstDev& I, const double (&m0
     return f;
 }
 
+// the shape-independent part of the gather (bin runs, far arrivals, count),
+// kept when a cell is retried with more particle slots per thread
+struct GatherState {
+    bool ready;
+    int n0, nwin, nfc;
+    uint32_t err;
+};
+
+// One cell with PPT slots per thread.  Returns 0 when the cell is done (or
+// the instance has failed) and 1 or 2 when it needs more slots than this
+// shape has; then nothing of the cell has been written: with retry_local the
+// caller reruns it with a larger shape (the gather state is reused), else
+// the cell is appended to tier_out for the next launch.  carve_cap is the
+// slot count the LDS tables are laid out for (the largest shape of the launch).
 template <int NT, typename real, int DIM, int PPT>
-__device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char* smem, int tid,
-                               int g, int* tier_out, int tier_len)
+__device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
+                                              unsigned char* smem, int tid, int g, int* tier_out,
+                                              int tier_len, int carve_cap, bool retry_local,
+                                              GatherState& gs)
 {
     const int* ctl = I.ctl;
-    if (ctl[CTL_ERR] != 0) return;
+    if (ctl[CTL_ERR] != 0) return 0;
     const int cur = ctl[CTL_CUR];
     const uint32_t step = (uint32_t)ctl[CTL_STEP];
     const int nsamp = ctl[CTL_NSAMP];
     const int nb = I.nb;
     constexpr int CAP = PPT * NT;
-    const Lds L = carve(smem, CAP, nb);
+    const Lds L = carve(smem, carve_cap, nb);
     const int ix = c % I.nx, iy = c / I.nx;
     const bool per_x = I.face_kind[0] == 2, per_y = I.face_kind[2] == 2;
     uint32_t errbits = 0;
     double* dg = I.diag ? I.diag + (size_t)c * NDIAG : nullptr;
-    // hand the cell to the next larger shape (nothing of it written yet)
-    const bool can_defer = tier_out != nullptr;
-    auto defer = [&]() {
-        if (tid == 0) {
+    // hand the cell to a larger shape (nothing of it written yet)
+    const bool can_defer = retry_local || tier_out != nullptr;
+    auto defer = [&](int code) -> int {
+        if (!retry_local && tid == 0) {
             const int k = atomicAdd(&tier_out[0], 1);
             if (k < tier_len) tier_out[1 + k] = g;
             else atomicOr(&I.ctl[CTL_ERR], (int)ERR_CAPACITY);  // lists not cleared
         }
+        return code;
     };
     long long tmark = clock64();
     auto mark = [&](int k) {
@@ -621,6 +638,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
     };
     Parts<real, DIM, PPT> P;
 
+    if (!gs.ready) {
     // per-cell inputs of the lane-0 sections, loaded while the gather runs
     if (tid < 41) {
         double v = 0.0;
@@ -707,16 +725,22 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
         L.run_dst[b] = L.run_pre[b] + sh;
     }
     __syncthreads();
-    const int nwin = (int)L.run_pre[nb];
-    int n0 = nwin + nfc;
+    gs.nwin = (int)L.run_pre[nb];
+    gs.nfc = nfc;
+    gs.n0 = gs.nwin + nfc;
+    gs.err = errbits;
+    gs.ready = true;
+    }
+    const int nfc = gs.nfc, nwin = gs.nwin;
+    int n0 = gs.n0;
+    errbits |= gs.err;
     if (can_defer && n0 <= I.max_ppc) {
-        // expected particles added in this launch: about n / r_p per batch
+        // particles added in this launch: S0 / r_p per batch (S0 of the
+        // cell's previous moments standing in for the current one)
         const int nbat = ((mode & MODE_RELAX) ? 2 : 0) + ((mode & MODE_MOVE) ? 1 : 0);
-        const double est = n0 + nbat * (1.1 * n0 / I.r_p + 8.0);
-        if (n0 > CAP || est > (double)CAP) {
-            defer();
-            return;
-        }
+        const double sp = fmax(L.pre[26], 0.0);
+        const double est = n0 + nbat * (1.1 * sp / I.r_p + 8.0);
+        if (n0 > CAP || est > (double)CAP) return defer(1);
     }
     if (n0 > I.max_ppc || n0 > CAP) {
         errbits |= ERR_CAPACITY;
@@ -829,10 +853,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
             // step 4
             const int n4 = spawn_r<NT>(I, P, L, 4, c, ix, iy, step, f, Pn, n0, n0, tid, &errbits,
                                    &mcnt, can_defer);
-            if (n4 < 0) {
-                defer();
-                return;
-            }
+            if (n4 < 0) return defer(2);
             const int nl = n0 + n4;
             mark(2);
             // step 5
@@ -887,10 +908,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
             // step 7
             const int n7 = spawn_r<NT>(I, P, L, 7, c, ix, iy, step, f, Pn, nl, nl, tid, &errbits,
                                    &mcnt, can_defer);
-            if (n7 < 0) {
-                defer();
-                return;
-            }
+            if (n7 < 0) return defer(2);
             nphys = nl + n7;
             mark(6);
             // conservation of the cell's mass, momentum and energy
@@ -1082,10 +1100,7 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
         // step 2 of the next time level
         const int n2 = spawn_r<NT>(I, P, L, 2, c, ix, iy, mstep, f, P2, nphys, nlog, tid, &errbits,
                                &mc2, can_defer);
-        if (n2 < 0) {
-            defer();
-            return;
-        }
+        if (n2 < 0) return defer(2);
         commit();
         nphys += n2;
         nlog += n2;
@@ -1229,9 +1244,10 @@ __device__ void process_cell_r(const InstDev& I, int c, int mode, unsigned char*
         for (int o = 32; o > 0; o >>= 1) e |= __shfl_xor(e, o, 64);
         if ((tid & 63) == 0) atomicOr(&I.ctl[CTL_ERR], (int)e);
     }
+    return 0;
 }
 
-template <typename real, int DIM, int NT, int PPT>
+template <typename real, int DIM, int NT, int PPT, int PPT2>
 __global__ void __launch_bounds__(NT) cell_kernel(Batch B)
 {
     // one workgroup per cell (no loop over cells: a loop would let the
@@ -1251,16 +1267,29 @@ __global__ void __launch_bounds__(NT) cell_kernel(Batch B)
         if (B.base[mid] <= g) lo = mid;
         else hi = mid - 1;
     }
-    process_cell_r<NT, real, DIM, PPT>(B.inst[lo], g - B.base[lo], B.mode, smem, tid, g,
-                                       B.tier_out, B.ncells);
+    GatherState gs;
+    gs.ready = false;
+    const InstDev& I = B.inst[lo];
+    const int c = g - B.base[lo];
+    if constexpr (PPT2 == 0) {
+        process_cell_r<NT, real, DIM, PPT>(I, c, B.mode, smem, tid, g, B.tier_out, B.ncells,
+                                           NT * PPT, false, gs);
+    } else {
+        // PPT slots per thread first; cells that need more rerun with PPT2
+        if (process_cell_r<NT, real, DIM, PPT>(I, c, B.mode, smem, tid, g, nullptr, 0, NT * PPT2,
+                                               true, gs) != 0)
+            process_cell_r<NT, real, DIM, PPT2>(I, c, B.mode, smem, tid, g, B.tier_out, B.ncells,
+                                                NT * PPT2, false, gs);
+    }
 }
 
-#define USP_CELL_INST(R, D, NT, PPT) template __global__ void cell_kernel<R, D, NT, PPT>(Batch);
-#define USP_CELL_ALL(R, D)       \
-    USP_CELL_INST(R, D, 256, 1)  \
-    USP_CELL_INST(R, D, 256, 2)  \
-    USP_CELL_INST(R, D, 256, 4)  \
-    USP_CELL_INST(R, D, 256, 6)  \
-    USP_CELL_INST(R, D, 512, 4)
+#define USP_CELL_INST(R, D, NT, PPT, PPT2) \
+    template __global__ void cell_kernel<R, D, NT, PPT, PPT2>(Batch);
+#define USP_CELL_ALL(R, D)            \
+    USP_CELL_INST(R, D, 256, 1, 0)    \
+    USP_CELL_INST(R, D, 256, 2, 0)    \
+    USP_CELL_INST(R, D, 256, 4, 0)    \
+    USP_CELL_INST(R, D, 256, 4, 6)    \
+    USP_CELL_INST(R, D, 512, 4, 0)
 
 }  // namespace usp

@@ -125,19 +125,21 @@ inline size_t lds_bytes(int cap, int nb)
 // Slot columns beyond a cell's count are skipped at run time, so a larger
 // shape costs registers and LDS, not instructions.
 struct Shape {
-    int nt, ppt;
+    int nt, ppt, ppt2;  // ppt2 > 0: cells that need more than nt x ppt slots rerun with ppt2
+    int slots() const { return nt * (ppt2 > ppt ? ppt2 : ppt); }
 };
 constexpr int NSHAPE = 5;
-constexpr Shape SHAPES[NSHAPE] = {{256, 1}, {256, 2}, {256, 4}, {256, 6}, {512, 4}};
+constexpr Shape SHAPES[NSHAPE] = {
+    {256, 1, 0}, {256, 2, 0}, {256, 4, 0}, {256, 4, 6}, {512, 4, 0}};
 inline int pick_shape_index(int max_ppc)
 {
     const int need = max_ppc + max_ppc / 8 + 1;
     for (int i = 0; i + 1 < NSHAPE; ++i)
-        if (need <= SHAPES[i].nt * SHAPES[i].ppt) return i;
+        if (need <= SHAPES[i].slots()) return i;
     return NSHAPE - 1;
 }
 inline Shape pick_shape(int max_ppc) { return SHAPES[pick_shape_index(max_ppc)]; }
-// the first shape a cell is tried with when its instance needs a larger one
-constexpr int TIER_FIRST = 2;
+// the first launch shape of an instance that needs the largest one
+constexpr int TIER_FIRST = 3;
 
 }  // namespace usp

@@ -21,7 +21,7 @@
 #include "usp_common.h"
 
 namespace usp {
-template <typename real, int DIM, int NT, int PPT>
+template <typename real, int DIM, int NT, int PPT, int PPT2>
 __global__ void cell_kernel(Batch B);
 template <typename real, int DIM>
 __global__ void init_kernel(Batch B, const double* init_n, const double* init_u,
@@ -206,12 +206,12 @@ usp_status with_kernel(int prec, int dim, F f)
 template <typename real, int D>
 const void* cell_kernel_for(Shape sh)
 {
-    if (sh.nt == 512) return (const void*)cell_kernel<real, D, 512, 4>;
+    if (sh.nt == 512) return (const void*)cell_kernel<real, D, 512, 4, 0>;
+    if (sh.ppt2 == 6) return (const void*)cell_kernel<real, D, 256, 4, 6>;
     switch (sh.ppt) {
-        case 1: return (const void*)cell_kernel<real, D, 256, 1>;
-        case 2: return (const void*)cell_kernel<real, D, 256, 2>;
-        case 4: return (const void*)cell_kernel<real, D, 256, 4>;
-        default: return (const void*)cell_kernel<real, D, 256, 6>;
+        case 1: return (const void*)cell_kernel<real, D, 256, 1, 0>;
+        case 2: return (const void*)cell_kernel<real, D, 256, 2, 0>;
+        default: return (const void*)cell_kernel<real, D, 256, 4, 0>;
     }
 }
 
@@ -255,7 +255,7 @@ usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int max_nb, int
         const Shape sh = SHAPES[t];
         B.tier_in = t == lo ? nullptr : B.tiers + (size_t)(t - 1) * B.tier_stride;
         B.tier_out = t == top ? nullptr : B.tiers + (size_t)t * B.tier_stride;
-        const size_t lds = lds_bytes(sh.ppt * sh.nt, max_nb);
+        const size_t lds = lds_bytes(sh.slots(), max_nb);
         st = with_kernel(prec, dim, [&](auto* rp, auto dimc) -> usp_status {
             using real = std::remove_pointer_t<decltype(rp)>;
             constexpr int D = decltype(dimc)::value;
