@@ -116,6 +116,31 @@ __device__ __forceinline__ void bsum(double (&v)[K], double* red, int tid)
     }
 }
 
+// the same where only some waves hold data (active is wave-uniform): the
+// others skip their shuffles and add zeros
+template <int NT, int K>
+__device__ __forceinline__ void bsum_part(double (&v)[K], double* red, int tid, bool active)
+{
+    constexpr int NW = NT / 64;
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave * K + k] = active ? v[k] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += red[w * K + k];
+        v[k] = s;
+    }
+}
+
 template <int NT>
 __device__ __forceinline__ double bmin(double v, double* red, int tid)
 {
@@ -206,8 +231,8 @@ __device__ __forceinline__ int fate(const Parts<real, DIM, PPT>& P, int k)
 }
 
 // ---------------------------------------------------------------------------
-// moments of the live particles (fate keep or reassigned): centred (two
-// passes) and raw sums; E = sum w |c|^2 / 2.  Every thread gets the results.
+// moments of the live particles (fate keep or reassigned): raw sums in one
+// pass, centred from them; E = sum w |c|^2 / 2.  Every thread gets the results.
 // ---------------------------------------------------------------------------
 template <int NT, typename real, int DIM, int PPT>
 __device__ void moments_r(const Parts<real, DIM, PPT>& P, const Lds& L, int tid, int nuse,
@@ -239,44 +264,15 @@ __device__ void moments_r(const Parts<real, DIM, PPT>& P, const Lds& L, int tid,
         }
     }
     bsum<NT>(a, L.red, tid);
-    const double s0 = a[0];
-    double U[3] = {0.0, 0.0, 0.0};
-    if (s0 != 0.0)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) U[q] = a[1 + q] / s0;
-    double b[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) b[q] = 0.0;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        if (k * NT < nuse && fate(P, k) <= FT_REASSIGN) {
-            const double w = (double)P.w[k];
-            const double C0 = (double)P.c0[k] - U[0], C1 = (double)P.c1[k] - U[1];
-            const double C2 = (double)P.c2[k] - U[2];
-            const double CC = C0 * C0 + C1 * C1 + C2 * C2;
-            b[0] += w * C0 * C0;
-            b[1] += w * C1 * C1;
-            b[2] += w * C2 * C2;
-            b[3] += w * C0 * C1;
-            b[4] += w * C0 * C2;
-            b[5] += w * C1 * C2;
-            b[6] += w * CC * C0;
-            b[7] += w * CC * C1;
-            b[8] += w * CC * C2;
-        }
-    }
-    bsum<NT>(b, L.red, tid);
-    cen[0] = s0;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) cen[1 + q] = U[q];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) cen[4 + q] = b[q];
+    // centred moments from the raw sums (FP64: the cancellation costs
+    // (|u|^2 / theta) of the 53 bits, far below the state precision)
     *E = a[4];
     raw[0] = a[0];
 #pragma unroll
     for (int q = 0; q < 3; ++q) raw[1 + q] = a[1 + q];
 #pragma unroll
     for (int q = 0; q < 9; ++q) raw[4 + q] = a[5 + q];
+    centred_from_raw(raw, cen);
 }
 
 // ---------------------------------------------------------------------------
@@ -337,10 +333,12 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
         double g[20];
 #pragma unroll
         for (int q = 0; q < 20; ++q) g[q] = 0.0;
+        bool mine = false;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int j = k * NT + tid;
             if (k * NT + NT > a && k * NT < a + na && j >= a && j < a + na) {
+                mine = true;
                 double psi[5];
                 psi5((double)P.c0[k], (double)P.c1[k], (double)P.c2[k], f.U, sq, f.theta, psi);
                 const double w = (double)P.w[k];
@@ -353,7 +351,10 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
                 for (int r1 = 0; r1 < 5; ++r1) g[15 + r1] += w * psi[r1];
             }
         }
-        bsum<NT>(g, L.red, tid);
+        // only the waves holding the batch reduce, solve and update
+        const bool wave_has = __ballot(mine) != 0;
+        bsum_part<NT>(g, L.red, tid, wave_has);
+        if (!wave_has) return na;
         // 5x5 Gram solve, unrolled in registers (the same values in every
         // lane): Cholesky G = L L^T, then L y = b and L^T lam = y
         double Lm[5][5];
@@ -416,15 +417,15 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
 
 // ---------------------------------------------------------------------------
 // f_G(t) velocity of one reassigned particle (Table 2 step 6; Eq. 6c, 29-32).
-// The time-sample uniform is word 2 of the particle's selection draw.
+// The time-sample uniform is word 2 (rt) of the particle's selection draw.
 // ---------------------------------------------------------------------------
 template <typename real>
 __device__ __forceinline__ int resample_one(const InstDev& I, int cell, int slot, uint32_t step,
-                                            const CellF& f, double pne, real& c0, real& c1,
-                                            real& c2)
+                                            const CellF& f, double pne, uint32_t rt, real& c0,
+                                            real& c1, real& c2)
 {
     uint32_t r[4];
-    draw(I, step, PUR_SELECT, 0u, (uint32_t)cell, (uint32_t)slot, r);
+    r[2] = rt;
     double alpha;
     if (sizeof(real) == 4) {
         const float u = uni_f(r[2]);
@@ -860,6 +861,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             const double psel = -expm1(-f.x);
             double ss[2] = {0.0, 0.0};
             double msel = __builtin_inf();
+            uint32_t rtime[PPT];  // word 2 of the selection draw: the f_G(t) time sample
             const int nlu = uni(nl);
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -871,6 +873,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                     const bool sel = u < psel;
                     msel = fmin(msel, fabs(u - psel));
                     P.key[k] = (r[1] & 0xFFFFF800u) | (uint32_t)j;
+                    rtime[k] = r[2];
                     if (sel) {
                         P.st[k] = (P.st[k] & ~0xFFu) | FT_SEL;
                         ss[0] += (double)P.w[k];
@@ -900,8 +903,8 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
                 if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
-                    fbs[0] += (double)resample_one(I, c, k * NT + tid, step, f, Pn, P.c0[k],
-                                                   P.c1[k], P.c2[k]);
+                    fbs[0] += (double)resample_one(I, c, k * NT + tid, step, f, Pn, rtime[k],
+                                                   P.c0[k], P.c1[k], P.c2[k]);
                     P.w[k] = (real)1.0;
                 }
             mark(5);
