@@ -80,7 +80,7 @@ def workload():
     return [tc, sod]
 
 
-def cpu_baseline(steps=8):
+def cpu_baseline(steps=30):
     """the CPU oracle (single thread, as it stands) on the same two problems
     for a few steps from their initial state"""
     from oracle import oracle as O
@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=20, help="steps per library call")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch eagerly instead of replaying captured HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -126,6 +128,7 @@ def main():
     ctx = usp.Context(0)
     ctx.set_block(args.block)
     inst = [ctx.add(pb) for pb in pbs]
+    ctx.set_graph(not args.no_graph)
 
     def run(n):
         left = n
@@ -179,6 +182,7 @@ def main():
             "cells": sum(pb.ncell for pb in pbs),
             "live_particles": int(n_live),
             "steps_per_call": args.chunk,
+            "hip_graph": not args.no_graph,
             "block": args.block,
         },
         "roofline": {

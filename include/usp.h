@@ -134,8 +134,13 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
                              const double* init_u, const double* init_T, int* id_out);
 usp_status usp_instance_free(usp_ctx* ctx, int id);
 
-/* Advances the n_ids listed instances by nsteps time steps each, all of them
- * in the same kernel launches (batched).  Asynchronous on the stream. */
+/* Advances the n_ids listed instances by nsteps time steps each (Table 2
+ * steps 2-8 per step).  Instances of one kernel flavour (state precision,
+ * dimension, launch shape) share every kernel launch (batched); flavours run
+ * side by side on internal streams forked from and joined back to the
+ * context's stream.  Asynchronous: returns once the work is enqueued.
+ * Errors: USP_EINVAL (no ids), USP_ESTATE (unknown, freed or failed id),
+ * USP_ENOMEM (batch tables), USP_EDEVICE (HIP launch or capture failure). */
 usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps);
 
 /* Waits for the stream; reports the first sticky instance error, if any. */
@@ -175,8 +180,18 @@ usp_status usp_get_diag(usp_ctx* ctx, int id, double* out);
  * is the only accepted value; others return USP_EINVAL. */
 usp_status usp_set_block(usp_ctx* ctx, int threads);
 
-/* Kernel timing (benchmarking): while on, every launch of the fused cell
- * kernel is bracketed by two HIP events on the context's stream.
+/* Graph replay (a11 of the step: the fused, batched step captured once).
+ * While on, the first usp_step call for a given list of instances and step
+ * count is captured into a HIP graph (kernels only: no memory set or copy is
+ * recorded) and launched; later calls with the same ids and nsteps replay
+ * that graph on the context's stream.  Results are bit-identical to eager
+ * launches.  Graphs are dropped when an instance is created or freed.
+ * Timing mode (below) launches eagerly.  Returns USP_EINVAL for a null ctx. */
+usp_status usp_set_graph(usp_ctx* ctx, int on);
+
+/* Kernel timing (benchmarking): while on, every pass of the fused cell
+ * kernel (all its shape launches) is bracketed by two HIP events on the
+ * stream it runs on.
  * usp_get_timing synchronises and returns the summed event time of those
  * launches (ms) and their number since timing was switched on. */
 usp_status usp_set_timing(usp_ctx* ctx, int on);

@@ -59,16 +59,30 @@ struct usp_ctx {
     // kernel timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-    // device descriptor tables of launch groups, keyed by their instance ids
+    // device descriptor tables of launch groups, keyed by their instance ids,
+    // with the group's shape-tier lists (NSHAPE x (1 + ncells) ints)
     struct Group {
         InstDev* d = nullptr;
         int* base = nullptr;
         size_t bytes = 0;
+        int* tiers = nullptr;
+        size_t tier_bytes = 0;
     };
     std::map<std::vector<int>, Group> groups;
-    // lists of the per-cell shape tiers (NSHAPE x (1 + tier_cells) ints)
+    // shape-tier lists of single-instance launches (initial / loaded states)
     int* tiers = nullptr;
     int tier_cells = 0;
+    // dynamic LDS limit already set per kernel
+    std::map<const void*, size_t> lds_set;
+    // concurrent launch groups: one side stream each (default priority),
+    // forked from and joined back to the caller's stream with events
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
+    // graph replay of whole usp_step calls, keyed by (instance ids, steps)
+    bool graph = false;
+    hipStream_t cap = nullptr;
+    std::map<std::vector<int>, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -236,60 +250,85 @@ void attach_tiers(usp_ctx* ctx, Batch& B)
     B.tier_stride = 1 + ctx->tier_cells;
 }
 
-// one cell-kernel pass over the batch.  Instances that need more particle
-// slots than the 256 x 4 shape run every cell with that shape first; a cell
-// that turns out to need more is handed on, untouched, to the next shape.
-usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int max_nb, int top)
+usp_status set_lds(usp_ctx* ctx, const void* kern, size_t lds)
 {
-    usp_status st = ensure_tiers(ctx, B.ncells);
-    if (st) return st;
-    attach_tiers(ctx, B);
+    auto it = ctx->lds_set.find(kern);
+    if (it != ctx->lds_set.end() && it->second >= lds) return USP_OK;
+    HIPCHK(ctx, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ctx->lds_set[kern] = lds;
+    return USP_OK;
+}
+
+// the kernels of one cell pass with their dynamic LDS sizes
+template <typename F>
+usp_status for_each_tier(int prec, int dim, int max_nb, int top, F f)
+{
     const int lo = std::min(top, TIER_FIRST);
+    for (int t = lo; t <= top; ++t) {
+        const Shape sh = SHAPES[t];
+        const size_t lds = lds_bytes(sh.slots(), max_nb);
+        usp_status st = with_kernel(prec, dim, [&](auto* rp, auto dimc) -> usp_status {
+            using real = std::remove_pointer_t<decltype(rp)>;
+            constexpr int D = decltype(dimc)::value;
+            return f(t, lo, sh, cell_kernel_for<real, D>(sh), lds);
+        });
+        if (st) return st;
+    }
+    return USP_OK;
+}
+
+usp_status prepare_cell(usp_ctx* ctx, int prec, int dim, int max_nb, int top)
+{
+    return for_each_tier(prec, dim, max_nb, top,
+                         [&](int, int, Shape, const void* kern, size_t lds) {
+                             return set_lds(ctx, kern, lds);
+                         });
+}
+
+// one cell-kernel pass over the batch (B.tiers set by the caller).
+// Instances that need more particle slots than the 256 x (4 | 6) shape run
+// every cell with it first; a cell that needs more is handed on, untouched,
+// to the 512-thread shape through the tier list.
+usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int max_nb, int top,
+                       hipStream_t stream)
+{
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->timing) {
         HIPCHK(ctx, hipEventCreate(&e0));
         HIPCHK(ctx, hipEventCreate(&e1));
-        HIPCHK(ctx, hipEventRecord(e0, ctx->stream));
+        HIPCHK(ctx, hipEventRecord(e0, stream));
     }
-    for (int t = lo; t <= top; ++t) {
-        const Shape sh = SHAPES[t];
-        B.tier_in = t == lo ? nullptr : B.tiers + (size_t)(t - 1) * B.tier_stride;
-        B.tier_out = t == top ? nullptr : B.tiers + (size_t)t * B.tier_stride;
-        const size_t lds = lds_bytes(sh.slots(), max_nb);
-        st = with_kernel(prec, dim, [&](auto* rp, auto dimc) -> usp_status {
-            using real = std::remove_pointer_t<decltype(rp)>;
-            constexpr int D = decltype(dimc)::value;
-            const void* kern = cell_kernel_for<real, D>(sh);
-            HIPCHK(ctx, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)lds));
+    usp_status st = for_each_tier(
+        prec, dim, max_nb, top,
+        [&](int t, int lo, Shape sh, const void* kern, size_t lds) -> usp_status {
+            usp_status s2 = set_lds(ctx, kern, lds);
+            if (s2) return s2;
+            B.tier_in = t == lo ? nullptr : B.tiers + (size_t)(t - 1) * B.tier_stride;
+            B.tier_out = t == top ? nullptr : B.tiers + (size_t)t * B.tier_stride;
             void* args[] = {(void*)&B};
-            HIPCHK(ctx,
-                   hipLaunchKernel(kern, dim3(B.ncells), dim3(sh.nt), args, lds, ctx->stream));
+            HIPCHK(ctx, hipLaunchKernel(kern, dim3(B.ncells), dim3(sh.nt), args, lds, stream));
             return USP_OK;
         });
-        if (st) return st;
-    }
+    if (st) return st;
     if (ctx->timing) {
-        HIPCHK(ctx, hipEventRecord(e1, ctx->stream));
+        HIPCHK(ctx, hipEventRecord(e1, stream));
         ctx->events.emplace_back(e0, e1);
     }
     return USP_OK;
 }
 
-usp_status launch_fields(usp_ctx* ctx, const Batch& B, int init)
+usp_status launch_fields(usp_ctx* ctx, const Batch& B, int init, hipStream_t stream)
 {
     const int nt = 256;
-    hipLaunchKernelGGL(fields_kernel, dim3((B.ncells + nt - 1) / nt), dim3(nt), 0, ctx->stream, B,
+    hipLaunchKernelGGL(fields_kernel, dim3((B.ncells + nt - 1) / nt), dim3(nt), 0, stream, B,
                        init);
     HIPCHK(ctx, hipGetLastError());
     return USP_OK;
 }
 
-usp_status launch_ctl(usp_ctx* ctx, Batch B, int relaxed)
+usp_status launch_ctl(usp_ctx* ctx, const Batch& B, int relaxed, hipStream_t stream)
 {
-    attach_tiers(ctx, B);
-    hipLaunchKernelGGL(ctl_kernel, dim3((B.ninst + 63) / 64), dim3(64), 0, ctx->stream, B,
-                       relaxed);
+    hipLaunchKernelGGL(ctl_kernel, dim3((B.ninst + 63) / 64), dim3(64), 0, stream, B, relaxed);
     HIPCHK(ctx, hipGetLastError());
     return USP_OK;
 }
@@ -330,9 +369,12 @@ usp_status err_status(usp_ctx* ctx, int e)
 void drop_groups(usp_ctx* ctx)
 {
     (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
     for (auto& kv : ctx->groups) {
         dfree(ctx, kv.second.d, kv.second.bytes);
         dfree(ctx, kv.second.base, 0);
+        dfree(ctx, kv.second.tiers, kv.second.tier_bytes);
     }
     ctx->groups.clear();
 }
@@ -341,11 +383,14 @@ void drop_groups(usp_ctx* ctx)
 usp_status finish_state(usp_ctx* ctx, Instance* in)
 {
     Batch B = single_batch(in, MODE_MOMENTS);
-    usp_status s = launch_cell(ctx, B, in->h.prec, in->h.dim, in->h.nb,
-                               pick_shape_index(in->h.max_ppc));
+    usp_status s = ensure_tiers(ctx, B.ncells);
     if (s) return s;
-    if ((s = launch_fields(ctx, B, 1))) return s;
-    return launch_ctl(ctx, B, 0);
+    attach_tiers(ctx, B);
+    if ((s = launch_cell(ctx, B, in->h.prec, in->h.dim, in->h.nb, pick_shape_index(in->h.max_ppc),
+                         ctx->stream)))
+        return s;
+    if ((s = launch_fields(ctx, B, 1, ctx->stream))) return s;
+    return launch_ctl(ctx, B, 0, ctx->stream);
 }
 
 }  // namespace
@@ -376,6 +421,12 @@ void usp_destroy(usp_ctx* ctx)
     for (Instance* in : ctx->inst) delete in;
     drop_groups(ctx);
     if (ctx->tiers) dfree(ctx, ctx->tiers, sizeof(int) * NSHAPE * (size_t)(1 + ctx->tier_cells));
+    for (size_t i = 0; i < ctx->side.size(); ++i) {
+        (void)hipStreamDestroy(ctx->side[i]);
+        (void)hipEventDestroy(ctx->join[i]);
+    }
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
 }
 
@@ -569,11 +620,21 @@ usp_status usp_set_block(usp_ctx* ctx, int threads)
     return USP_OK;
 }
 
-usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps)
+}  // extern "C"
+
+namespace {
+
+// one launch group of a usp_step call: instances of one kernel flavour
+struct Plan {
+    Batch B;
+    int prec, dim, max_nb, top;
+};
+
+// groups the instances by kernel flavour (precision, dimension, shape) and
+// makes sure their descriptor tables, tier lists and kernel attributes exist
+// (all of it before any launch: a graph capture may follow)
+usp_status make_plan(usp_ctx* ctx, const int* ids, int n_ids, std::vector<Plan>& plans)
 {
-    if (!ctx || !ids || n_ids <= 0) return fail(ctx, USP_EINVAL, "no instances");
-    if (nsteps <= 0) return USP_OK;
-    // group the instances by kernel flavour (precision, dimension, shape)
     for (int i = 0; i < n_ids; ++i)
         if (!get_inst(ctx, ids[i])) return fail(ctx, USP_ESTATE, "unknown or freed instance in step");
     for (int g = 0; g < 4 * NSHAPE; ++g) {
@@ -586,7 +647,11 @@ usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps)
                 sel.push_back(ids[i]);
         }
         if (sel.empty()) continue;
-        // device descriptor table of this group (kept while the group exists)
+        int ncells = 0, max_nb = 0;
+        for (int id : sel) {
+            ncells += ctx->inst[id]->h.ncell;
+            max_nb = std::max(max_nb, ctx->inst[id]->h.nb);
+        }
         std::vector<int> key = sel;
         key.push_back(-1 - g);
         auto it = ctx->groups.find(key);
@@ -595,7 +660,14 @@ usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps)
             G.bytes = sizeof(InstDev) * sel.size();
             G.d = (InstDev*)dalloc(ctx, G.bytes);
             G.base = (int*)dalloc(ctx, sizeof(int) * (sel.size() + 1));
-            if (!G.d || !G.base) return fail(ctx, USP_ENOMEM, "batch table");
+            G.tier_bytes = sizeof(int) * NSHAPE * (size_t)(1 + ncells);
+            G.tiers = (int*)dalloc(ctx, G.tier_bytes);
+            if (!G.d || !G.base || !G.tiers) {
+                dfree(ctx, G.d, G.bytes);
+                dfree(ctx, G.base, 0);
+                dfree(ctx, G.tiers, G.tier_bytes);
+                return fail(ctx, USP_ENOMEM, "batch table");
+            }
             std::vector<InstDev> hd;
             std::vector<int> base(1, 0);
             for (int id : sel) {
@@ -606,30 +678,120 @@ usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps)
                                        ctx->stream));
             HIPCHK(ctx, hipMemcpyAsync(G.base, base.data(), sizeof(int) * base.size(),
                                        hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(ctx, hipMemsetAsync(G.tiers, 0, G.tier_bytes, ctx->stream));
             HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
             it = ctx->groups.emplace(key, G).first;
         }
-        Batch B;
-        B.inst = it->second.d;
-        B.base = it->second.base;
-        B.ninst = (int)sel.size();
-        B.ncells = 0;
-        int max_nb = 0;
-        for (int id : sel) {
-            B.ncells += ctx->inst[id]->h.ncell;
-            max_nb = std::max(max_nb, ctx->inst[id]->h.nb);
-        }
-        usp_status s;
-        B.mode = MODE_MOVE;
-        if ((s = launch_cell(ctx, B, prec, dim, max_nb, g >> 2))) return s;
-        if ((s = launch_ctl(ctx, B, 0))) return s;
-        for (int k = 0; k < nsteps; ++k) {
-            B.mode = k + 1 < nsteps ? (MODE_RELAX | MODE_MOVE) : MODE_RELAX;
-            if ((s = launch_cell(ctx, B, prec, dim, max_nb, g >> 2))) return s;
-            if ((s = launch_fields(ctx, B, 0))) return s;
-            if ((s = launch_ctl(ctx, B, 1))) return s;
-        }
+        Plan P;
+        P.B.inst = it->second.d;
+        P.B.base = it->second.base;
+        P.B.ninst = (int)sel.size();
+        P.B.ncells = ncells;
+        P.B.tiers = it->second.tiers;
+        P.B.tier_stride = 1 + ncells;
+        P.prec = prec;
+        P.dim = dim;
+        P.max_nb = max_nb;
+        P.top = g >> 2;
+        usp_status st = prepare_cell(ctx, prec, dim, max_nb, P.top);
+        if (st) return st;
+        plans.push_back(P);
     }
+    return USP_OK;
+}
+
+// the launches of nsteps steps of one group on one stream: a move pass, then
+// per step a relax (+ move) pass, the P_ne field and the step control
+usp_status enqueue_group(usp_ctx* ctx, Plan P, int nsteps, hipStream_t st)
+{
+    usp_status s;
+    P.B.mode = MODE_MOVE;
+    if ((s = launch_cell(ctx, P.B, P.prec, P.dim, P.max_nb, P.top, st))) return s;
+    if ((s = launch_ctl(ctx, P.B, 0, st))) return s;
+    for (int k = 0; k < nsteps; ++k) {
+        P.B.mode = k + 1 < nsteps ? (MODE_RELAX | MODE_MOVE) : MODE_RELAX;
+        if ((s = launch_cell(ctx, P.B, P.prec, P.dim, P.max_nb, P.top, st))) return s;
+        if ((s = launch_fields(ctx, P.B, 0, st))) return s;
+        if ((s = launch_ctl(ctx, P.B, 1, st))) return s;
+    }
+    return USP_OK;
+}
+
+usp_status ensure_side(usp_ctx* ctx, size_t n)
+{
+    if (!ctx->fork) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    while (ctx->side.size() < n) {
+        hipStream_t s2 = nullptr;
+        hipEvent_t e2 = nullptr;
+        HIPCHK(ctx, hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        HIPCHK(ctx, hipEventCreateWithFlags(&e2, hipEventDisableTiming));
+        ctx->side.push_back(s2);
+        ctx->join.push_back(e2);
+    }
+    return USP_OK;
+}
+
+// all groups: one group runs on the origin stream; several run side by side
+// on their own streams, forked from and joined back to the origin
+usp_status enqueue_all(usp_ctx* ctx, const std::vector<Plan>& plans, int nsteps, hipStream_t origin)
+{
+    if (plans.size() == 1) return enqueue_group(ctx, plans[0], nsteps, origin);
+    usp_status s = ensure_side(ctx, plans.size());
+    if (s) return s;
+    HIPCHK(ctx, hipEventRecord(ctx->fork, origin));
+    for (size_t i = 0; i < plans.size(); ++i) {
+        HIPCHK(ctx, hipStreamWaitEvent(ctx->side[i], ctx->fork, 0));
+        if ((s = enqueue_group(ctx, plans[i], nsteps, ctx->side[i]))) return s;
+        HIPCHK(ctx, hipEventRecord(ctx->join[i], ctx->side[i]));
+        HIPCHK(ctx, hipStreamWaitEvent(origin, ctx->join[i], 0));
+    }
+    return USP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps)
+{
+    if (!ctx || !ids || n_ids <= 0) return fail(ctx, USP_EINVAL, "no instances");
+    if (nsteps <= 0) return USP_OK;
+    std::vector<Plan> plans;
+    usp_status s = make_plan(ctx, ids, n_ids, plans);
+    if (s) return s;
+    if (!ctx->graph || ctx->timing) return enqueue_all(ctx, plans, nsteps, ctx->stream);
+    // graph mode: capture the whole call once, replay it afterwards
+    std::vector<int> key(ids, ids + n_ids);
+    key.push_back(-nsteps);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        if (!ctx->cap) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+        if (plans.size() > 1 && (s = ensure_side(ctx, plans.size()))) return s;
+        HIPCHK(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+        s = enqueue_all(ctx, plans, nsteps, ctx->cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ctx->cap, &graph);
+        if (s) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        if (ec != hipSuccess || !graph)
+            return fail(ctx, USP_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess)
+            return fail(ctx, USP_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        it = ctx->graphs.emplace(key, exec).first;
+    }
+    HIPCHK(ctx, hipGraphLaunch(it->second, ctx->stream));
+    return USP_OK;
+}
+
+usp_status usp_set_graph(usp_ctx* ctx, int on)
+{
+    if (!ctx) return USP_EINVAL;
+    ctx->graph = on != 0;
     return USP_OK;
 }
 

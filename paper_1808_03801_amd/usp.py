@@ -98,6 +98,7 @@ def lib():
             "usp_set_block": (C.c_int, [vp, C.c_int]),
             "usp_philox": (C.c_int, [vp, u32p, C.c_uint32, C.c_uint32, C.c_int, u32p]),
             "usp_set_timing": (C.c_int, [vp, C.c_int]),
+            "usp_set_graph": (C.c_int, [vp, C.c_int]),
             "usp_get_timing": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
         }
         for name, (res, args) in sig.items():
@@ -114,7 +115,7 @@ def exported_symbols():
             "usp_instance_free", "usp_step", "usp_sync", "usp_instance_status", "usp_num_cells",
             "usp_num_particles", "usp_get_state", "usp_set_state", "usp_get_fields",
             "usp_set_diag", "usp_get_diag", "usp_set_block", "usp_philox", "usp_set_timing",
-            "usp_get_timing"]
+            "usp_get_timing", "usp_set_graph"]
 
 
 def _dp(a):
@@ -249,6 +250,10 @@ class Context:
 
     def set_timing(self, on: bool):
         _check(self.h, lib().usp_set_timing(self.h, int(on)))
+
+    def set_graph(self, on: bool):
+        """capture each distinct step call into a HIP graph and replay it"""
+        _check(self.h, lib().usp_set_graph(self.h, int(on)))
 
     def timing(self):
         """(summed fused-kernel event time in ms, number of launches)"""
