@@ -14,6 +14,8 @@ Prints one JSON line (see the "roofline" and "cpu_baseline" members).
 """
 import argparse
 import hashlib
+
+import numpy as np
 import json
 import os
 import re
@@ -99,6 +101,40 @@ def cpu_baseline(steps=30):
                        f"({n0}-{n1} live particles), {dt:.1f} s")
 
 
+def serving(n, steps, budget):
+    """The request mix of the serving workload (Poisson arrivals at 50/s,
+    Couette / Poiseuille / Sod, Kn log-uniform in [1e-3, 1], 50-400 cells,
+    50-200 particles per cell, steps uniform in `steps`), served with
+    continuous batching and, for comparison, one request at a time."""
+    import torch
+    from paper_1808_03801_amd import serve as S
+    from paper_1808_03801_amd import usp
+    reqs = S.request_trace(n, rate=50.0, steps=steps, seed=0)
+    ctx = usp.Context(0)
+    srv = S.Server(ctx, budget=budget, chunk=50)
+    futs = [srv.submit(r) for r in reqs]
+    t0 = time.perf_counter()
+    srv.run(t0=t0)
+    wall_b = time.perf_counter() - t0
+    batched = [f.result() for f in futs]
+    t0 = time.perf_counter()
+    plain = S.run_plain(ctx, reqs, t0=t0)
+    wall_p = time.perf_counter() - t0
+    same = all(
+        np.array_equal(b.fields, p.fields)
+        for b, p in zip(sorted(batched, key=lambda r: r.request.seed),
+                        sorted(plain, key=lambda r: r.request.seed)))
+    ctx.close()
+    sb, sp = S.summarize(batched, wall_b), S.summarize(plain, wall_p)
+    return {
+        "requests": n, "steps_per_request": list(steps), "arrival_rate_per_s": 50.0,
+        "hbm_budget_bytes": budget, "max_active": srv.max_active,
+        "batched": sb, "plain": sp,
+        "speedup_solves_per_s": sb["solves_per_s"] / sp["solves_per_s"],
+        "results_identical_to_plain": bool(same),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +145,11 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--no-graph", action="store_true",
                     help="launch eagerly instead of replaying captured HIP graphs")
+    ap.add_argument("--serve", type=int, default=64,
+                    help="requests of the serving measurement (0: skip it)")
+    ap.add_argument("--serve-steps", default="200,1000",
+                    help="step range of the serving requests (the full mix: 2000,10000)")
+    ap.add_argument("--serve-budget", type=float, default=2.0, help="HBM budget, GiB")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -197,11 +238,14 @@ def main():
             "bytes_per_launch": bytes_per_launch,
         },
     }
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline()
     for i in inst:
         i.free()
     ctx.close()
+    if args.serve > 0:
+        lo, hi = (int(v) for v in args.serve_steps.split(","))
+        line["serving"] = serving(args.serve, (lo, hi), int(args.serve_budget * (1 << 30)))
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
 
 

@@ -28,7 +28,7 @@
 
 namespace usp {
 
-constexpr int MAX_NW = 8;  // waves per workgroup at most (512 threads)
+constexpr int MAX_NW = 4;  // waves per workgroup (256 threads)
 constexpr int FAR_BIN = 0xFFFF;
 constexpr uint32_t FARBIT = 0x80000000u;
 
@@ -51,6 +51,7 @@ struct Lds {
     uint32_t* fib;
     uint32_t* fcount;
     double* sc;
+    double* psb;   // [PSB][6] basis values and weight of added particles (Gram sums)
     CellF* f;      // cell scalars shared by the workgroup
     double* mom;   // [0..12] centred, [13..25] averages, [26] energy, [27..29] momentum
     double* pend;  // [0..12] raw sums, [13..25] J-moment averages, [26] count: stored
@@ -85,6 +86,7 @@ __device__ __forceinline__ Lds carve(unsigned char* sm, int cap, int nb)
     L.fib = (uint32_t*)take((size_t)FAR_LDS * 4);
     L.fcount = (uint32_t*)take(16);
     L.sc = (double*)take(64 * 8);
+    L.psb = (double*)take((size_t)PSB * 6 * 8);
     L.f = (CellF*)take(sizeof(CellF));
     L.mom = (double*)take(32 * 8);
     L.pend = (double*)take(32 * 8);
@@ -106,31 +108,6 @@ __device__ __forceinline__ void bsum(double (&v)[K], double* red, int tid)
     if (lane == 0)
 #pragma unroll
         for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) s += red[w * K + k];
-        v[k] = s;
-    }
-}
-
-// the same where only some waves hold data (active is wave-uniform): the
-// others skip their shuffles and add zeros
-template <int NT, int K>
-__device__ __forceinline__ void bsum_part(double (&v)[K], double* red, int tid, bool active)
-{
-    constexpr int NW = NT / 64;
-    if (active) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-    }
-    const int lane = tid & 63, wave = tid >> 6;
-    __syncthreads();
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < K; ++k) red[wave * K + k] = active ? v[k] : 0.0;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -330,31 +307,52 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
         }
     }
     if (I.proj && na >= 5) {
-        double g[20];
-#pragma unroll
-        for (int q = 0; q < 20; ++q) g[q] = 0.0;
+        // Gram matrix and right-hand side summed in batch order (the order
+        // the batch was drawn in), independent of where the batch sits in
+        // the registers: each batch particle leaves (psi, w) in LDS, chunk
+        // by chunk, and lane e of wave 0 accumulates entry e serially.
+        int er = 0, es = 0;
+        if (tid < 15) {
+            while ((er + 1) * (er + 2) / 2 <= tid) ++er;
+            es = tid - er * (er + 1) / 2;
+        }
+        double acc = 0.0;
         bool mine = false;
+        for (int q0 = 0; q0 < na; q0 += PSB) {
+            __syncthreads();
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int j = k * NT + tid;
-            if (k * NT + NT > a && k * NT < a + na && j >= a && j < a + na) {
-                mine = true;
-                double psi[5];
-                psi5((double)P.c0[k], (double)P.c1[k], (double)P.c2[k], f.U, sq, f.theta, psi);
-                const double w = (double)P.w[k];
-                int q = 0;
+            for (int k = 0; k < PPT; ++k) {
+                const int j = k * NT + tid;
+                if (k * NT + NT > a && k * NT < a + na && j >= a + q0 && j < a + na &&
+                    j < a + q0 + PSB) {
+                    mine = true;
+                    double psi[5];
+                    psi5((double)P.c0[k], (double)P.c1[k], (double)P.c2[k], f.U, sq, f.theta,
+                         psi);
+                    double* ps = L.psb + 6 * (j - a - q0);
 #pragma unroll
-                for (int r1 = 0; r1 < 5; ++r1)
-#pragma unroll
-                    for (int s1 = 0; s1 <= r1; ++s1) g[q++] += psi[r1] * psi[s1];
-#pragma unroll
-                for (int r1 = 0; r1 < 5; ++r1) g[15 + r1] += w * psi[r1];
+                    for (int r1 = 0; r1 < 5; ++r1) ps[r1] = psi[r1];
+                    ps[5] = (double)P.w[k];
+                }
+            }
+            __syncthreads();
+            if (tid < 20) {
+                const int nq = na - q0 < PSB ? na - q0 : PSB;
+                if (tid < 15) {
+                    for (int q = 0; q < nq; ++q) acc += L.psb[6 * q + er] * L.psb[6 * q + es];
+                } else {
+                    for (int q = 0; q < nq; ++q) acc += L.psb[6 * q + 5] * L.psb[6 * q + tid - 15];
+                }
             }
         }
-        // only the waves holding the batch reduce, solve and update
-        const bool wave_has = __ballot(mine) != 0;
-        bsum_part<NT>(g, L.red, tid, wave_has);
-        if (!wave_has) return na;
+        __syncthreads();
+        if (tid < 20) L.sc[tid] = acc;
+        __syncthreads();
+        // only the waves holding the batch solve and update
+        if (__ballot(mine) == 0) return na;
+        double g[20];
+#pragma unroll
+        for (int q = 0; q < 20; ++q) g[q] = L.sc[q];
         // 5x5 Gram solve, unrolled in registers (the same values in every
         // lane): Cholesky G = L L^T, then L y = b and L^T lam = y
         double Lm[5][5];
@@ -1293,6 +1291,6 @@ __global__ void __launch_bounds__(NT) cell_kernel(Batch B)
     USP_CELL_INST(R, D, 256, 2, 0)    \
     USP_CELL_INST(R, D, 256, 4, 0)    \
     USP_CELL_INST(R, D, 256, 4, 6)    \
-    USP_CELL_INST(R, D, 512, 4, 0)
+    USP_CELL_INST(R, D, 256, 8, 0)
 
 }  // namespace usp

@@ -12,6 +12,7 @@ constexpr int NDIAG_STEP = 32;  // slots describing the last step; then phase cy
 constexpr int MAX_BINS = 256;
 constexpr int MAX_PPC = 2048;
 constexpr int FAR_LDS = 128;  // far arrivals one cell can take per step
+constexpr int PSB = 256;      // added particles per chunk of the batch-order Gram sums
 
 // control words of an instance (device memory)
 enum { CTL_CUR = 0, CTL_STEP = 1, CTL_NSAMP = 2, CTL_ERR = 3, CTL_N = 4 };
@@ -109,10 +110,11 @@ inline size_t lds_bytes(int cap, int nb)
     b += r16((size_t)cap * 4);                  // gather map
     b += r16((size_t)(cap / 64) * nb * 2);      // bin tile counts
     b += r16(256 * 4) + r16(64 * 4);            // histogram, scan totals
-    b += r16(8 * 24 * 8);                       // reductions (up to 8 waves)
+    b += r16(4 * 24 * 8);                       // reductions (4 waves)
     b += 4 * r16((size_t)(nb + 1) * 4);         // runs, bin offsets
     b += r16((size_t)FAR_LDS * 8) + 3 * r16((size_t)FAR_LDS * 4) + r16(16);  // far arrivals
     b += r16(64 * 8);                           // scalars
+    b += r16((size_t)PSB * 6 * 8);              // Gram-sum staging
     b += r16(32 * 8);                           // pending moments
     b += r16(48 * 8);                           // per-cell inputs
     b += r16(256) + r16(32 * 8);                // cell scalars, moments
@@ -121,16 +123,20 @@ inline size_t lds_bytes(int cap, int nb)
 
 // launch shape of the cell kernel (threads per cell, particle slots per
 // thread) for a largest cell of max_ppc particles, with room for the step-2
-// particles of a full cell.  At most 6 slots per thread: more spill registers.
-// Slot columns beyond a cell's count are skipped at run time, so a larger
-// shape costs registers and LDS, not instructions.
+// particles of a full cell.  Slot columns beyond a cell's count are skipped
+// at run time, so a larger shape costs registers and LDS, not instructions.
+// Every shape has 256 threads: particle j always sits in thread j mod 256,
+// so every reduction adds the same numbers in the same order whatever shape
+// runs a cell.  6 slots per thread is the most that fits the registers at two
+// workgroups per CU; the 8-slot shape (it spills) serves the rare cells of
+// more than 1536 particles.
 struct Shape {
     int nt, ppt, ppt2;  // ppt2 > 0: cells that need more than nt x ppt slots rerun with ppt2
     int slots() const { return nt * (ppt2 > ppt ? ppt2 : ppt); }
 };
 constexpr int NSHAPE = 5;
 constexpr Shape SHAPES[NSHAPE] = {
-    {256, 1, 0}, {256, 2, 0}, {256, 4, 0}, {256, 4, 6}, {512, 4, 0}};
+    {256, 1, 0}, {256, 2, 0}, {256, 4, 0}, {256, 4, 6}, {256, 8, 0}};
 inline int pick_shape_index(int max_ppc)
 {
     const int need = max_ppc + max_ppc / 8 + 1;

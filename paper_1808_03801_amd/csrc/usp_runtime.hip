@@ -220,12 +220,12 @@ usp_status with_kernel(int prec, int dim, F f)
 template <typename real, int D>
 const void* cell_kernel_for(Shape sh)
 {
-    if (sh.nt == 512) return (const void*)cell_kernel<real, D, 512, 4, 0>;
     if (sh.ppt2 == 6) return (const void*)cell_kernel<real, D, 256, 4, 6>;
     switch (sh.ppt) {
         case 1: return (const void*)cell_kernel<real, D, 256, 1, 0>;
         case 2: return (const void*)cell_kernel<real, D, 256, 2, 0>;
-        default: return (const void*)cell_kernel<real, D, 256, 4, 0>;
+        case 4: return (const void*)cell_kernel<real, D, 256, 4, 0>;
+        default: return (const void*)cell_kernel<real, D, 256, 8, 0>;
     }
 }
 
@@ -288,7 +288,7 @@ usp_status prepare_cell(usp_ctx* ctx, int prec, int dim, int max_nb, int top)
 // one cell-kernel pass over the batch (B.tiers set by the caller).
 // Instances that need more particle slots than the 256 x (4 | 6) shape run
 // every cell with it first; a cell that needs more is handed on, untouched,
-// to the 512-thread shape through the tier list.
+// to the 8-slot shape through the tier list.
 usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int max_nb, int top,
                        hipStream_t stream)
 {

@@ -248,3 +248,30 @@ def test_graph_replay_matches_eager():
         c.set_graph(False)
     finally:
         c.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["thermal_couette_fp32", "sod_fp32_tiers", "cavity_fp32"])
+def test_step_calls_split_anywhere_give_the_same_state(name):
+    """k steps in one call (relax of step n fused with the move of step n+1)
+    against the same k steps one call each (a relax-only and a move-only pass
+    per step) and against uneven calls: bit-identical states"""
+    usp = _gpu()
+    pb = _cases()[name]()
+    c = usp.Context(0)
+    try:
+        a, b, d = c.add(pb), c.add(pb), c.add(pb)
+        c.step([a], 12)
+        for _ in range(12):
+            c.step([b], 1)
+        for k in (5, 2, 4, 1):
+            c.step([d], k)
+        c.sync()
+        sa = a.get_state()
+        for x in (b, d):
+            sx = x.get_state()
+            assert np.array_equal(sa.counts, sx.counts)
+            assert np.array_equal(sa.parts, sx.parts)
+            assert np.array_equal(sa.cells, sx.cells)
+    finally:
+        c.close()
