@@ -1,0 +1,67 @@
+"""Parity at the full sizes of the workloads, in the launch configuration the
+benchmark times (instances batched in one launch, HIP-graph replay).
+
+The oracle takes a few steps from the initial state, its state is loaded into
+the library, and both take one more step; the comparison protocol is the one
+of tests/parity_util.py (bit-exact counts, decisions and particle order;
+values to the state precision; moments to 1e-5)."""
+import numpy as np
+import pytest
+
+import bench
+from oracle import oracle as O
+from paper_1808_03801_amd import problems as P
+from tests.parity_util import compare_step
+
+
+def _oracle_states(pbs, warm):
+    out = []
+    for pb in pbs:
+        o = O.Oracle(pb)
+        o.step(warm)
+        assert o.error == 0
+        out.append(o.get_state())
+    return out
+
+
+def _parity(pbs, warm=2, graph=True):
+    from paper_1808_03801_amd import usp
+    sts = _oracle_states(pbs, warm)
+    ctx = usp.Context(0)
+    try:
+        ctx.set_graph(graph)
+        gs = [ctx.add(pb) for pb in pbs]
+        for g, st in zip(gs, sts):
+            g.set_diag(True)
+            g.set_state(st)
+        ctx.step(gs, 1)
+        ctx.sync()
+        for pb, g, st in zip(pbs, gs, sts):
+            o = O.Oracle(pb)
+            o.set_state(st)
+            o.step(1)
+            rep = {}
+            compare_step(pb, o.get_state(), g.get_state(), o.diag(), g.diag(), o.fields(0),
+                         g.fields(0), report=rep)
+            print(pb.name, pb.ncell, "cells", int(st.counts.sum()), "particles", rep)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.gpu
+def test_thermal_couette_and_sod_full_size_batched():
+    """1000 cells x 500 particles/cell each, FP32, both in every launch"""
+    _parity(bench.workload())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kn", [1e-3, 0.1])
+def test_cavity_full_size(kn):
+    """128 x 128 cells x 200 particles/cell (3.3 M), FP32"""
+    _parity([P.cavity_2d(Kn=kn, seed=21)])
+
+
+@pytest.mark.gpu
+def test_couette_c1_full_size():
+    """100 cells x 100 particles/cell, FP64, hard spheres, walls +-100 m/s"""
+    _parity([P.couette_1d(seed=0)], warm=5)
