@@ -180,7 +180,22 @@ usp_status usp_get_diag(usp_ctx* ctx, int id, double* out);
  * is the only accepted value; others return USP_EINVAL. */
 usp_status usp_set_block(usp_ctx* ctx, int threads);
 
-/* Graph replay (a11 of the step: the fused, batched step captured once).
+/* Launch shapes of the cell kernel.  Shape s (0 <= s < nshape) holds a cell
+ * in 256 threads x {1, 2, 4, 4|6, 8}[s] particle slots per thread (4|6: the
+ * cell reruns with 6 slots when 4 are too few).  An instance's last shape is
+ * the smallest that holds max_ppc; its first shape (default: the last, or
+ * shape 3 when the last is 4) runs every cell, and cells that need more
+ * slots are handed on, before anything of them is written, to the following
+ * shapes up to the last.  Every shape computes bit-identical results (all
+ * use 256 threads and the same reduction order), so the choice only changes
+ * speed: usp_set_shape is the knob an autotuner turns.  first = -1 restores
+ * the default.  Errors: USP_ESTATE (unknown id), USP_EINVAL (first outside
+ * [-1, last]).  usp_get_shape returns the first and last shape in use and
+ * the number of shapes. */
+usp_status usp_set_shape(usp_ctx* ctx, int id, int first);
+usp_status usp_get_shape(usp_ctx* ctx, int id, int* first, int* last, int* nshape);
+
+/* Graph replay (the fused, batched step captured once).
  * While on, the first usp_step call for a given list of instances and step
  * count is captured into a HIP graph (kernels only: no memory set or copy is
  * recorded) and launched; later calls with the same ids and nsteps replay

@@ -316,7 +316,7 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
             while ((er + 1) * (er + 2) / 2 <= tid) ++er;
             es = tid - er * (er + 1) / 2;
         }
-        double acc = 0.0;
+        double acc4[4] = {0.0, 0.0, 0.0, 0.0};
         bool mine = false;
         for (int q0 = 0; q0 < na; q0 += PSB) {
             __syncthreads();
@@ -337,16 +337,23 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
             }
             __syncthreads();
             if (tid < 20) {
+                // four running sums over q mod 4 (a fixed order: the loads of
+                // successive particles overlap), joined after the last chunk
                 const int nq = na - q0 < PSB ? na - q0 : PSB;
-                if (tid < 15) {
-                    for (int q = 0; q < nq; ++q) acc += L.psb[6 * q + er] * L.psb[6 * q + es];
-                } else {
-                    for (int q = 0; q < nq; ++q) acc += L.psb[6 * q + 5] * L.psb[6 * q + tid - 15];
+                const int ea = tid < 15 ? er : 5, eb = tid < 15 ? es : tid - 15;
+                int q = 0;
+                for (; q + 4 <= nq; q += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        acc4[u] += L.psb[6 * (q + u) + ea] * L.psb[6 * (q + u) + eb];
                 }
+#pragma unroll
+                for (int u = 0; u < 3; ++u)
+                    if (q + u < nq) acc4[u] += L.psb[6 * (q + u) + ea] * L.psb[6 * (q + u) + eb];
             }
         }
         __syncthreads();
-        if (tid < 20) L.sc[tid] = acc;
+        if (tid < 20) L.sc[tid] = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
         __syncthreads();
         // only the waves holding the batch solve and update
         if (__ballot(mine) == 0) return na;
@@ -988,7 +995,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                 }
             }
             double fbt[1] = {fbs[0]};
-            bsum<NT>(fbt, L.red, tid);
+            if (dg) bsum<NT>(fbt, L.red, tid);  // diagnostics only
             mark(7);
             // logical slots of the survivors (slot order), step-7 particles last
             {
@@ -1156,6 +1163,9 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
         for (int q = tid; q < ntl * nb; q += NT) L.tiles[q] = 0;
         __syncthreads();
         const int lane = tid & 63;
+        // lanes of a wave that share a bin, found bit by bit of the bin
+        // index (one ballot per bit instead of one per distinct bin)
+        const int nbits = 32 - __clz(nb - 1 > 0 ? nb - 1 : 1);
         uint32_t rank[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -1164,14 +1174,19 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             const int b = (int)P.key[k];
             const int tile = j >> 6;
             rank[k] = 0;
-            uint64_t rem = __ballot(act);
-            while (rem) {
-                const int leader = __ffsll((unsigned long long)rem) - 1;
-                const int bv = __builtin_amdgcn_readlane(b, leader);
-                const uint64_t mm = __ballot(act && b == bv);
-                if (lane == leader) L.tiles[tile * nb + bv] = (uint16_t)__popcll(mm);
-                if (act && b == bv) rank[k] = (uint32_t)__popcll(mm & lanemask_lt(lane));
-                rem &= ~mm;
+            if (k * NT >= npu2) continue;
+            uint64_t peers = __ballot(act);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                if (bit < nbits) {
+                    const bool on = act && ((b >> bit) & 1);
+                    const uint64_t m = __ballot(on);
+                    peers &= ((b >> bit) & 1) ? m : ~m;
+                }
+            }
+            if (act) {
+                rank[k] = (uint32_t)__popcll(peers & lanemask_lt(lane));
+                if (rank[k] == 0) L.tiles[tile * nb + b] = (uint16_t)__popcll(peers);
             }
         }
         __syncthreads();

@@ -45,6 +45,9 @@ struct Instance {
     size_t bytes = 0;
     bool alive = false;
     bool diag_on = false;
+    int first = -1;       // first launch shape (-1: the default)
+    int top() const { return pick_shape_index(h.max_ppc); }
+    int first_shape() const { return first >= 0 ? first : std::min(top(), TIER_FIRST); }
 };
 
 }  // namespace
@@ -261,9 +264,9 @@ usp_status set_lds(usp_ctx* ctx, const void* kern, size_t lds)
 
 // the kernels of one cell pass with their dynamic LDS sizes
 template <typename F>
-usp_status for_each_tier(int prec, int dim, int max_nb, int top, F f)
+usp_status for_each_tier(int prec, int dim, int max_nb, int first, int top, F f)
 {
-    const int lo = std::min(top, TIER_FIRST);
+    const int lo = std::min(first, top);
     for (int t = lo; t <= top; ++t) {
         const Shape sh = SHAPES[t];
         const size_t lds = lds_bytes(sh.slots(), max_nb);
@@ -277,9 +280,9 @@ usp_status for_each_tier(int prec, int dim, int max_nb, int top, F f)
     return USP_OK;
 }
 
-usp_status prepare_cell(usp_ctx* ctx, int prec, int dim, int max_nb, int top)
+usp_status prepare_cell(usp_ctx* ctx, int prec, int dim, int max_nb, int first, int top)
 {
-    return for_each_tier(prec, dim, max_nb, top,
+    return for_each_tier(prec, dim, max_nb, first, top,
                          [&](int, int, Shape, const void* kern, size_t lds) {
                              return set_lds(ctx, kern, lds);
                          });
@@ -289,7 +292,7 @@ usp_status prepare_cell(usp_ctx* ctx, int prec, int dim, int max_nb, int top)
 // Instances that need more particle slots than the 256 x (4 | 6) shape run
 // every cell with it first; a cell that needs more is handed on, untouched,
 // to the 8-slot shape through the tier list.
-usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int max_nb, int top,
+usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int max_nb, int first, int top,
                        hipStream_t stream)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -299,7 +302,7 @@ usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int max_nb, int
         HIPCHK(ctx, hipEventRecord(e0, stream));
     }
     usp_status st = for_each_tier(
-        prec, dim, max_nb, top,
+        prec, dim, max_nb, first, top,
         [&](int t, int lo, Shape sh, const void* kern, size_t lds) -> usp_status {
             usp_status s2 = set_lds(ctx, kern, lds);
             if (s2) return s2;
@@ -386,7 +389,7 @@ usp_status finish_state(usp_ctx* ctx, Instance* in)
     usp_status s = ensure_tiers(ctx, B.ncells);
     if (s) return s;
     attach_tiers(ctx, B);
-    if ((s = launch_cell(ctx, B, in->h.prec, in->h.dim, in->h.nb, pick_shape_index(in->h.max_ppc),
+    if ((s = launch_cell(ctx, B, in->h.prec, in->h.dim, in->h.nb, in->first_shape(), in->top(),
                          ctx->stream)))
         return s;
     if ((s = launch_fields(ctx, B, 1, ctx->stream))) return s;
@@ -627,7 +630,7 @@ namespace {
 // one launch group of a usp_step call: instances of one kernel flavour
 struct Plan {
     Batch B;
-    int prec, dim, max_nb, top;
+    int prec, dim, max_nb, first, top;
 };
 
 // groups the instances by kernel flavour (precision, dimension, shape) and
@@ -637,23 +640,23 @@ usp_status make_plan(usp_ctx* ctx, const int* ids, int n_ids, std::vector<Plan>&
 {
     for (int i = 0; i < n_ids; ++i)
         if (!get_inst(ctx, ids[i])) return fail(ctx, USP_ESTATE, "unknown or freed instance in step");
-    for (int g = 0; g < 4 * NSHAPE; ++g) {
-        const int prec = (g & 1) ? 64 : 32, dim = (g & 2) ? 2 : 1;
-        std::vector<int> sel;
-        for (int i = 0; i < n_ids; ++i) {
-            Instance* in = get_inst(ctx, ids[i]);
-            if (in->h.prec == prec && in->h.dim == dim &&
-                pick_shape_index(in->h.max_ppc) == (g >> 2))
-                sel.push_back(ids[i]);
-        }
-        if (sel.empty()) continue;
+    // flavour = (precision, dimension, first shape, last shape); the map
+    // keeps the groups in a fixed order
+    std::map<std::vector<int>, std::vector<int>> flavours;
+    for (int i = 0; i < n_ids; ++i) {
+        Instance* in = get_inst(ctx, ids[i]);
+        flavours[{in->h.prec, in->h.dim, in->first_shape(), in->top()}].push_back(ids[i]);
+    }
+    for (auto& fv : flavours) {
+        const int prec = fv.first[0], dim = fv.first[1], first = fv.first[2], top = fv.first[3];
+        const std::vector<int>& sel = fv.second;
         int ncells = 0, max_nb = 0;
         for (int id : sel) {
             ncells += ctx->inst[id]->h.ncell;
             max_nb = std::max(max_nb, ctx->inst[id]->h.nb);
         }
         std::vector<int> key = sel;
-        key.push_back(-1 - g);
+        key.push_back(-1 - (first * NSHAPE + top) * 4 - (prec == 64 ? 2 : 0) - (dim - 1));
         auto it = ctx->groups.find(key);
         if (it == ctx->groups.end()) {
             usp_ctx::Group G;
@@ -692,8 +695,9 @@ usp_status make_plan(usp_ctx* ctx, const int* ids, int n_ids, std::vector<Plan>&
         P.prec = prec;
         P.dim = dim;
         P.max_nb = max_nb;
-        P.top = g >> 2;
-        usp_status st = prepare_cell(ctx, prec, dim, max_nb, P.top);
+        P.first = first;
+        P.top = top;
+        usp_status st = prepare_cell(ctx, prec, dim, max_nb, first, top);
         if (st) return st;
         plans.push_back(P);
     }
@@ -706,11 +710,11 @@ usp_status enqueue_group(usp_ctx* ctx, Plan P, int nsteps, hipStream_t st)
 {
     usp_status s;
     P.B.mode = MODE_MOVE;
-    if ((s = launch_cell(ctx, P.B, P.prec, P.dim, P.max_nb, P.top, st))) return s;
+    if ((s = launch_cell(ctx, P.B, P.prec, P.dim, P.max_nb, P.first, P.top, st))) return s;
     if ((s = launch_ctl(ctx, P.B, 0, st))) return s;
     for (int k = 0; k < nsteps; ++k) {
         P.B.mode = k + 1 < nsteps ? (MODE_RELAX | MODE_MOVE) : MODE_RELAX;
-        if ((s = launch_cell(ctx, P.B, P.prec, P.dim, P.max_nb, P.top, st))) return s;
+        if ((s = launch_cell(ctx, P.B, P.prec, P.dim, P.max_nb, P.first, P.top, st))) return s;
         if ((s = launch_fields(ctx, P.B, 0, st))) return s;
         if ((s = launch_ctl(ctx, P.B, 1, st))) return s;
     }
@@ -785,6 +789,30 @@ usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps)
         it = ctx->graphs.emplace(key, exec).first;
     }
     HIPCHK(ctx, hipGraphLaunch(it->second, ctx->stream));
+    return USP_OK;
+}
+
+usp_status usp_set_shape(usp_ctx* ctx, int id, int first)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in) return fail(ctx, USP_ESTATE, "unknown or freed instance");
+    if (first < -1 || first > in->top())
+        return fail(ctx, USP_EINVAL, "first shape must be -1 or in [0, the instance's last shape]");
+    if (first != in->first) {
+        drop_groups(ctx);
+        in->first = first;
+    }
+    return USP_OK;
+}
+
+usp_status usp_get_shape(usp_ctx* ctx, int id, int* first, int* last, int* nshape)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in) return fail(ctx, USP_ESTATE, "unknown or freed instance");
+    if (!first || !last || !nshape) return fail(ctx, USP_EINVAL, "null output");
+    *first = in->first_shape();
+    *last = in->top();
+    *nshape = NSHAPE;
     return USP_OK;
 }
 

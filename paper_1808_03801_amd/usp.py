@@ -99,6 +99,9 @@ def lib():
             "usp_philox": (C.c_int, [vp, u32p, C.c_uint32, C.c_uint32, C.c_int, u32p]),
             "usp_set_timing": (C.c_int, [vp, C.c_int]),
             "usp_set_graph": (C.c_int, [vp, C.c_int]),
+            "usp_set_shape": (C.c_int, [vp, C.c_int, C.c_int]),
+            "usp_get_shape": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                        C.POINTER(C.c_int)]),
             "usp_get_timing": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
         }
         for name, (res, args) in sig.items():
@@ -115,7 +118,7 @@ def exported_symbols():
             "usp_instance_free", "usp_step", "usp_sync", "usp_instance_status", "usp_num_cells",
             "usp_num_particles", "usp_get_state", "usp_set_state", "usp_get_fields",
             "usp_set_diag", "usp_get_diag", "usp_set_block", "usp_philox", "usp_set_timing",
-            "usp_get_timing", "usp_set_graph"]
+            "usp_get_timing", "usp_set_graph", "usp_set_shape", "usp_get_shape"]
 
 
 def _dp(a):
@@ -324,6 +327,17 @@ class Instance:
         out = np.zeros((self.ncell, NDIAG))
         _check(self.ctx.h, lib().usp_get_diag(self.ctx.h, self.id, _dp(out)))
         return out
+
+    def set_shape(self, first: int):
+        """first launch shape of this instance (-1: default); results unchanged"""
+        _check(self.ctx.h, lib().usp_set_shape(self.ctx.h, self.id, int(first)))
+
+    def shape(self):
+        """(first shape, last shape, number of shapes)"""
+        a, b, n = C.c_int(), C.c_int(), C.c_int()
+        _check(self.ctx.h, lib().usp_get_shape(self.ctx.h, self.id, C.byref(a), C.byref(b),
+                                               C.byref(n)))
+        return a.value, b.value, n.value
 
     def free(self):
         _check(self.ctx.h, lib().usp_instance_free(self.ctx.h, self.id))

@@ -275,3 +275,40 @@ def test_step_calls_split_anywhere_give_the_same_state(name):
             assert np.array_equal(sa.cells, sx.cells)
     finally:
         c.close()
+
+
+@pytest.mark.gpu
+def test_every_launch_shape_and_the_autotuner_give_the_same_state():
+    """each first launch shape (handing dense cells on to larger ones) and
+    the autotuner's choice leave the solve bit-identical to the default"""
+    from paper_1808_03801_amd import autotune
+    usp = _gpu()
+    pb = _cases()["sod_fp32_tiers"]()
+    c = usp.Context(0)
+    try:
+        ref = c.add(pb)
+        first, last, nshape = ref.shape()
+        assert nshape == 5 and last == 4 and first == 3
+        forced = []
+        for s in range(last + 1):
+            x = c.add(pb)
+            x.set_shape(s)
+            assert x.shape()[0] == s
+            forced.append(x)
+        tuned = c.add(pb)
+        choice = autotune.tune(c, [tuned], steps=2, repeats=1)
+        n = autotune.tune.steps_taken
+        assert 0 <= choice[tuned.id] <= last and n == (last + 1) * 3
+        c.step([ref], n)
+        c.step(forced, n)
+        c.sync()
+        s0 = ref.get_state()
+        for x in forced + [tuned]:
+            sx = x.get_state()
+            assert np.array_equal(s0.counts, sx.counts), x.shape()
+            assert np.array_equal(s0.parts, sx.parts), x.shape()
+            assert np.array_equal(s0.cells, sx.cells), x.shape()
+        with pytest.raises(usp.UspError):
+            ref.set_shape(last + 1)
+    finally:
+        c.close()
