@@ -92,12 +92,16 @@ typedef struct {
  * and the ES target (instantaneous Eq. 1 or averaged Eq. 34);
  * spawn_projection: 1 = project each added batch onto zero mass, momentum and
  * energy; window: sort-window half width in cells (0 = derive from the
- * initial state). */
+ * initial state); avg_init: start of the Eq. 34 averages (both the averaged
+ * fields and the averages of f-tilde^* that jmom_mode uses): 0 = the first
+ * sample, then a running mean until n_avg samples; 1 = the exact raw moments
+ * of the initial Maxwellian state, then the fixed window n_avg. */
 typedef struct {
     double dt, Np, r_p, Kn_c, pne_fixed;
     int pne_mode, n_avg, avg_start, precision, weight_mode, conserve_mode, max_ppc;
     int jmom_mode, spawn_projection, window;
     uint64_t seed;
+    int avg_init;
 } usp_numerics;
 
 /* Device binding.  alloc/free: device allocator (NULL = hipMalloc/hipFree);

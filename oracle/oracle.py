@@ -39,7 +39,7 @@ class Config(C.Structure):
         ("pne_mode", C.c_int), ("n_avg", C.c_int), ("avg_start", C.c_int),
         ("precision", C.c_int), ("weight_mode", C.c_int), ("conserve_mode", C.c_int),
         ("max_ppc", C.c_int), ("jmom_mode", C.c_int), ("spawn_projection", C.c_int),
-        ("seed_lo", C.c_uint32), ("seed_hi", C.c_uint32),
+        ("seed_lo", C.c_uint32), ("seed_hi", C.c_uint32), ("avg_init", C.c_int),
     ]
 
 
@@ -112,6 +112,7 @@ def make_config(pb) -> Config:
     g.spawn_projection = pb.spawn_projection
     g.seed_lo = pb.seed & 0xFFFFFFFF
     g.seed_hi = (pb.seed >> 32) & 0xFFFFFFFF
+    g.avg_init = pb.avg_init
     return g
 
 

@@ -348,6 +348,85 @@ static void psi_basis(const double c[3], const double U[3], double sq, double th
     psi[4] = (C[0] * C[0] + C[1] * C[1] + C[2] * C[2]) / (2.0 * theta) - 1.5;
 }
 
+/* The same constraint (zero mass, momentum and energy of the batch) met by
+ * the smallest weight change that also leaves the batch's stress and heat
+ * flux sums untouched: the change is a combination of the 5 conserved
+ * functions psi and the 8 functions phi of the stress (traceless second
+ * order: X0 X1, X0 X2, X1 X2, X0^2 - X1^2, X1^2 - X2^2) and heat flux
+ * (X_i (|X|^2 / 2 - 5/2)), X = C / sqrt(theta), with sum dw psi = -sum w psi
+ * and sum dw phi = 0 (a 13x13 Gram system, Cholesky).  The plain projection
+ * above removes the part of the batch's stress that happens to lie in the
+ * span of psi over the batch's own velocities, about 5 / N_a of it, which
+ * lowers the viscosity by that fraction; this one does not.  Batches of
+ * fewer than 13 particles, or with a pivot not above 1e-10 of the first
+ * diagonal entry, are left unchanged. */
+static void basis13(const double c[3], const double U[3], double sq, double a[13])
+{
+    const double X0 = (c[0] - U[0]) / sq, X1 = (c[1] - U[1]) / sq, X2 = (c[2] - U[2]) / sq;
+    const double h = 0.5 * (X0 * X0 + X1 * X1 + X2 * X2);
+    a[0] = 1.0;
+    a[1] = X0;
+    a[2] = X1;
+    a[3] = X2;
+    a[4] = h - 1.5;
+    a[5] = X0 * X1;
+    a[6] = X0 * X2;
+    a[7] = X1 * X2;
+    a[8] = X0 * X0 - X1 * X1;
+    a[9] = X1 * X1 - X2 * X2;
+    a[10] = X0 * (h - 2.5);
+    a[11] = X1 * (h - 2.5);
+    a[12] = X2 * (h - 2.5);
+}
+
+static int project_batch13(const uspo_config* g, part* p, int n, const double U[3], double theta)
+{
+    enum { M = 13 };
+    if (n < M) return 0;
+    const double sq = sqrt(theta);
+    double G[M][M], b[M], a[M];
+    memset(G, 0, sizeof(G));
+    memset(b, 0, sizeof(b));
+    for (int k = 0; k < n; ++k) {
+        basis13(p[k].c, U, sq, a);
+        for (int i = 0; i < M; ++i) {
+            if (i < 5) b[i] -= p[k].w * a[i];
+            for (int j = 0; j <= i; ++j) G[i][j] += a[i] * a[j];
+        }
+    }
+    double L[M][M];
+    memset(L, 0, sizeof(L));
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double t = G[i][j];
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            if (i == j) {
+                if (!(t > 1e-10 * G[0][0])) return -1;
+                L[i][i] = sqrt(t);
+            } else {
+                L[i][j] = t / L[j][j];
+            }
+        }
+    double y[M], mu[M];
+    for (int i = 0; i < M; ++i) {
+        double t = b[i];
+        for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
+        y[i] = t / L[i][i];
+    }
+    for (int i = M - 1; i >= 0; --i) {
+        double t = y[i];
+        for (int k = i + 1; k < M; ++k) t -= L[k][i] * mu[k];
+        mu[i] = t / L[i][i];
+    }
+    for (int k = 0; k < n; ++k) {
+        basis13(p[k].c, U, sq, a);
+        double d = 0.0;
+        for (int i = 0; i < M; ++i) d += a[i] * mu[i];
+        p[k].w = st(g, p[k].w + d);
+    }
+    return 1;
+}
+
 static int project_batch(const uspo_config* g, part* p, int n, const double U[3], double theta)
 {
     if (n < 5) return 0;
@@ -429,7 +508,8 @@ static int spawn(const uspo* o, int batch, int cell, const cellf* f, double pne,
         q.w = st(g, -cw * grad_bracket(g, f, C) * factor);
         pl_push(L, q);
     }
-    if (g->spawn_projection) project_batch(g, L->p + (L->n - na), na, f->U, f->theta);
+    if (g->spawn_projection == 1) project_batch(g, L->p + (L->n - na), na, f->U, f->theta);
+    if (g->spawn_projection == 2) project_batch13(g, L->p + (L->n - na), na, f->U, f->theta);
     return na;
 }
 
@@ -667,6 +747,7 @@ static int resample(const uspo* o, const cellf* f, double pne, int cell, int slo
 static double avg_window(const uspo_config* g, int n_samples)
 {
     int k = n_samples + 1;
+    if (g->avg_init) return (double)g->n_avg;
     return (double)(k < g->n_avg ? k : g->n_avg);
 }
 
@@ -946,7 +1027,7 @@ static void update_pne(uspo* o, double* pout)
     }
     int* counts = (int*)malloc(sizeof(int) * (size_t)nc);
     for (int i = 0; i < nc; ++i) counts[i] = o->cell[i].n;
-    if (g->pne_mode == 2 && o->n_samples > 0) {
+    if (g->pne_mode == 2 && (o->n_samples > 0 || g->avg_init)) {
         double* m = (double*)malloc(sizeof(double) * USPO_MOM * (size_t)nc);
         for (int i = 0; i < nc; ++i) {
             centred_from_raw(o->avg + (size_t)USPO_MOM * i, m + (size_t)USPO_MOM * i);
@@ -1014,6 +1095,25 @@ uspo* uspo_create(const uspo_config* cfg, const double* init_n, const double* in
         int n = (int)floor(init_n[c] * g->vcell / g->Np + 0.5);
         if (n > g->max_ppc) o->error = -3;
         double sq = sqrt(g->kB * init_T[c] / g->m);
+        if (g->avg_init) {
+            /* raw sums of a Maxwellian of n particles at (u, theta): sum w = n,
+             * sum w c = n u, sum w c c = n (u u + theta I), sum w |c|^2 c =
+             * n (|u|^2 + 5 theta) u */
+            const double* u = init_u + 3 * c;
+            const double th = sq * sq, N = (double)n;
+            const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            double* A = o->avgs + (size_t)USPO_MOM * c;
+            A[0] = N;
+            for (int k = 0; k < 3; ++k) A[1 + k] = N * u[k];
+            A[4] = N * (u[0] * u[0] + th);
+            A[5] = N * (u[1] * u[1] + th);
+            A[6] = N * (u[2] * u[2] + th);
+            A[7] = N * u[0] * u[1];
+            A[8] = N * u[0] * u[2];
+            A[9] = N * u[1] * u[2];
+            for (int k = 0; k < 3; ++k) A[10 + k] = N * (u2 + 5.0 * th) * u[k];
+            memcpy(o->avg + (size_t)USPO_MOM * c, A, sizeof(double) * USPO_MOM);
+        }
         for (int k = 0; k < n; ++k) {
             part q;
             uint32_t r[4];
@@ -1058,7 +1158,7 @@ static void one_step(uspo* o)
     for (int c = 0; c < nc; ++c) {
         cellf f;
         derive(o, o->mom + (size_t)USPO_MOM * c, o->cell[c].n, &f);
-        if (g->jmom_mode == 1 && o->n_samples > 0 && f.valid)
+        if (g->jmom_mode == 1 && (o->n_samples > 0 || g->avg_init) && f.valid)
             use_averaged_sh(o, o->avg + (size_t)USPO_MOM * c, &f);
         double mg = INFINITY;
         int n2 = spawn(o, 2, c, &f, o->pprev[c], &o->cell[c], &mg);

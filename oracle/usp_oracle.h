@@ -41,6 +41,11 @@ typedef struct {
      * momentum and energy */
     int jmom_mode, spawn_projection;
     uint32_t seed_lo, seed_hi;
+    /* Eq. 34 start: 0 = the first sample, then a running mean until n_avg
+     * samples; 1 = the exact raw moments of the initial Maxwellian state,
+     * then the fixed window n_avg from the first sample (both averages: the
+     * Eq. 34 fields and the averages of f-tilde^*) */
+    int avg_init;
 } uspo_config;
 
 /* per-cell state record: centred moments, raw sums, averaged raw sums of f^n,

@@ -815,7 +815,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             if (tid < 64) {
                 const bool use_avg = I.jmom_mode == 1 && (int)step >= I.avg_start;
                 double A[NMOM];
-                const double ne = avg_window(I.n_avg, nsamp);
+                const double ne = avg_window(I.n_avg, nsamp, I.avg_init);
 #pragma unroll
                 for (int q = 0; q < NMOM; ++q)
                     A[q] = (ne - 1.0) / ne * L.pre[q] + 1.0 / ne * rawt[q];
@@ -1032,7 +1032,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             moments_r<NT>(P, L, tid, uni(nphys), cen1, raw1, &E1);
             if (tid == 0) {
                 L.pend[26] = (double)nlog;
-                const double ne = avg_window(I.n_avg, nsamp);
+                const double ne = avg_window(I.n_avg, nsamp, I.avg_init);
                 for (int q = 0; q < NMOM; ++q) {
                     Ms[q] = cen1[q];
                     L.pend[q] = raw1[q];
@@ -1099,7 +1099,8 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             }
             const int ns_after =
                 nsamp + (((mode & MODE_RELAX) && (int)step >= I.avg_start) ? 1 : 0);
-            const CellF fw = pair_derive(I, m, nlog, A, I.jmom_mode == 1 && ns_after > 0, tid);
+            const CellF fw = pair_derive(I, m, nlog, A,
+                                         I.jmom_mode == 1 && (ns_after > 0 || I.avg_init), tid);
             if (tid == 0) f = fw;
         }
         __syncthreads();

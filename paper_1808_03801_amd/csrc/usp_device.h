@@ -148,10 +148,12 @@ __device__ __forceinline__ double grad_bracket(double Pr, const CellF& f, const 
     return sCC / (2.0 * f.theta) + 0.4 * Pr * hC * (C2 / (2.0 * f.theta) - 2.5) / f.theta;
 }
 
-// Eq. 34 window: running mean for the first n_avg samples, then exponential
-__device__ __forceinline__ double avg_window(int n_avg, int n_samples)
+// Eq. 34 window: running mean for the first n_avg samples, then exponential;
+// with averages started from the exact initial moments, n_avg throughout
+__device__ __forceinline__ double avg_window(int n_avg, int n_samples, int avg_init)
 {
     const int k = n_samples + 1;
+    if (avg_init) return (double)n_avg;
     return (double)(k < n_avg ? k : n_avg);
 }
 

@@ -59,7 +59,7 @@ __global__ void fields_kernel(Batch B, int init)
     } else {
         const int step = I.ctl[CTL_STEP];
         const int ns_after = I.ctl[CTL_NSAMP] + ((!init && step >= I.avg_start) ? 1 : 0);
-        const bool use_avg = I.pne_mode == 2 && ns_after > 0;
+        const bool use_avg = I.pne_mode == 2 && (ns_after > 0 || I.avg_init);
         GllCell me;
         gll_cell(I, c, use_avg, me);
         if (!me.valid) {

@@ -496,6 +496,7 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
     h.max_ppc = nm->max_ppc;
     h.jmom_mode = nm->jmom_mode;
     h.proj = nm->spawn_projection;
+    h.avg_init = nm->avg_init != 0;
     h.key0 = (uint32_t)(nm->seed & 0xFFFFFFFFu);
     h.key1 = (uint32_t)(nm->seed >> 32);
     Window w = choose_window(gas, pb, nm, init_u, init_T);
@@ -561,8 +562,36 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
         delete in;
         return fail(ctx, USP_ENOMEM, "device allocation failed or over budget");
     }
-    HIPCHK(ctx, hipMemsetAsync(h.avg, 0, NMOM * ncell * 8, ctx->stream));
-    HIPCHK(ctx, hipMemsetAsync(h.avgs, 0, NMOM * ncell * 8, ctx->stream));
+    if (h.avg_init) {
+        // raw sums of the initial Maxwellian of each cell (N particles at
+        // u, theta): N, N u, N (u u + theta I), N (|u|^2 + 5 theta) u
+        std::vector<double> A0((size_t)NMOM * ncell);
+        for (size_t c = 0; c < ncell; ++c) {
+            const double N = (double)(int)floor(init_n[c] * pb->vcell / nm->Np + 0.5);
+            const double sq = sqrt(gas->kB * init_T[c] / gas->m), th = sq * sq;
+            const double* u = init_u + 3 * c;
+            const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            double a[NMOM];
+            a[0] = N;
+            for (int k = 0; k < 3; ++k) a[1 + k] = N * u[k];
+            a[4] = N * (u[0] * u[0] + th);
+            a[5] = N * (u[1] * u[1] + th);
+            a[6] = N * (u[2] * u[2] + th);
+            a[7] = N * u[0] * u[1];
+            a[8] = N * u[0] * u[2];
+            a[9] = N * u[1] * u[2];
+            for (int k = 0; k < 3; ++k) a[10 + k] = N * (u2 + 5.0 * th) * u[k];
+            for (int q = 0; q < NMOM; ++q) A0[(size_t)q * ncell + c] = a[q];
+        }
+        HIPCHK(ctx, hipMemcpyAsync(h.avg, A0.data(), NMOM * ncell * 8, hipMemcpyHostToDevice,
+                                   ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(h.avgs, A0.data(), NMOM * ncell * 8, hipMemcpyHostToDevice,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    } else {
+        HIPCHK(ctx, hipMemsetAsync(h.avg, 0, NMOM * ncell * 8, ctx->stream));
+        HIPCHK(ctx, hipMemsetAsync(h.avgs, 0, NMOM * ncell * 8, ctx->stream));
+    }
     HIPCHK(ctx, hipMemsetAsync(h.ctl, 0, CTL_N * 4, ctx->stream));
     HIPCHK(ctx, hipMemsetAsync(h.far_n, 0, 2 * sizeof(int), ctx->stream));
     int base[2] = {0, h.ncell};

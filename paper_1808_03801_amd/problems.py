@@ -126,6 +126,7 @@ class Problem:
     max_ppc: int = 2048
     jmom_mode: int = JMOM_INST
     spawn_projection: int = 0
+    avg_init: int = 0
     meta: dict = field(default_factory=dict)
 
     @property
@@ -184,7 +185,7 @@ def couette_1d(Kn=0.1, U_w=100.0, T_w=273.0, ncell=100, ppc=100, dt_over_tau=1.0
 
 def thermal_couette_1d(Kn=1e-3, dT=10.0, T_w=273.0, ncell=1000, ppc=500, dt_over_tau=5.0,
                        omega=0.81, precision=32, seed=0, init_ns=True,
-                       pne_mode=PNE_GLL_AVG, jmom_mode=JMOM_AVG, spawn_projection=1,
+                       pne_mode=PNE_GLL_AVG, jmom_mode=JMOM_AVG, spawn_projection=0, avg_init=1,
                        name="thermal_couette") -> Problem:
     """Stationary diffuse plates at T_w + dT (bottom) and T_w - dT (top)
     (Section 4.1).  With init_ns the gas starts on the Fourier profile of a
@@ -206,7 +207,7 @@ def thermal_couette_1d(Kn=1e-3, dT=10.0, T_w=273.0, ncell=1000, ppc=500, dt_over
                    accel=(0.0, 0.0, 0.0), dt=dt_over_tau * tau0, Np=n0 * g["vcell"] / ppc,
                    init_n=n, init_u=np.zeros((ncell, 3)), init_T=T, precision=precision,
                    seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
-                   spawn_projection=spawn_projection,
+                   spawn_projection=spawn_projection, avg_init=avg_init,
                    meta=dict(H=H, lam0=lam0, tau0=tau0, n0=n0, T_bottom=Tb, T_top=Tt, Kn=Kn)))
 
 
@@ -245,7 +246,7 @@ def sod_1d(Kn=1e-3, L=1.0, ncell=1000, mean_ppc=500, rho_ratio=8.0, p_ratio=10.0
 
 def poiseuille_1d(Kn=1e-3, dpdx=4.0e6, T_w=273.0, ncell=100, ppc=500, dt_over_tau=5.0,
                   omega=0.81, precision=32, seed=0, pne_mode=PNE_GLL_AVG,
-                  jmom_mode=JMOM_AVG, spawn_projection=1, name="poiseuille") -> Problem:
+                  jmom_mode=JMOM_AVG, spawn_projection=0, avg_init=1, name="poiseuille") -> Problem:
     """Plane Poiseuille flow (Section 4.2, Table 3) driven by a uniform body
     acceleration a_x = (dp/dx) / rho_0 along the plates."""
     gas = Gas(omega=omega)
@@ -258,13 +259,13 @@ def poiseuille_1d(Kn=1e-3, dpdx=4.0e6, T_w=273.0, ncell=100, ppc=500, dt_over_ta
                    Np=n0 * g["vcell"] / ppc, init_n=np.full(ncell, n0),
                    init_u=np.zeros((ncell, 3)), init_T=np.full(ncell, T_w),
                    precision=precision, seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
-                   spawn_projection=spawn_projection,
+                   spawn_projection=spawn_projection, avg_init=avg_init,
                    meta=dict(H=H, lam0=lam0, tau0=tau0, rho0=rho0, n0=n0, dpdx=dpdx, T_w=T_w,
                              Kn=Kn)))
 
 
 def cavity_2d(Kn=1e-3, n=128, ppc=200, U_lid=50.0, T_w=273.0, omega=0.81, precision=32,
-              seed=0, pne_mode=PNE_GLL_AVG, jmom_mode=JMOM_AVG, spawn_projection=1,
+              seed=0, pne_mode=PNE_GLL_AVG, jmom_mode=JMOM_AVG, spawn_projection=0, avg_init=1,
               name="cavity") -> Problem:
     """Lid-driven square cavity (Section 4.4): four diffuse walls at T_w, the
     top one moving at U_lid along x; dt = 0.3 dx / mean speed (the
@@ -281,7 +282,7 @@ def cavity_2d(Kn=1e-3, n=128, ppc=200, U_lid=50.0, T_w=273.0, omega=0.81, precis
                    accel=(0.0, 0.0, 0.0), dt=0.3 * d / gas.mean_speed(T_w),
                    Np=n0 * d * d / ppc, init_n=np.full(nc, n0), init_u=np.zeros((nc, 3)),
                    init_T=np.full(nc, T_w), precision=precision, seed=seed, pne_mode=pne_mode,
-                   jmom_mode=jmom_mode, spawn_projection=spawn_projection,
+                   jmom_mode=jmom_mode, spawn_projection=spawn_projection, avg_init=avg_init,
                    meta=dict(L=L, lam0=lam0, tau0=tau0, n0=n0, U_lid=U_lid, Kn=Kn)))
 
 
