@@ -56,6 +56,7 @@ struct Lds {
     double* mom;   // [0..12] centred, [13..25] averages, [26] energy, [27..29] momentum
     double* pend;  // [0..12] raw sums, [13..25] J-moment averages, [26] count: stored
                    // to HBM once the cell can no longer be handed to a larger shape
+    long long* tst;  // [16] phase time stamps (diagnostics), [15] = start
     double* pre;   // per-cell inputs loaded at the start: [0..12] J-moment averages,
                    // [13..25] Eq. 34 averages, [26..38] moments, [39] P_ne^n, [40] P_ne^n-1
 };
@@ -91,6 +92,7 @@ __device__ __forceinline__ Lds carve(unsigned char* sm, int cap, int nb)
     L.mom = (double*)take(32 * 8);
     L.pend = (double*)take(32 * 8);
     L.pre = (double*)take(48 * 8);
+    L.tst = (long long*)take(16 * 8);
     return L;
 }
 
@@ -619,6 +621,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     const int nsamp = ctl[CTL_NSAMP];
     const int nb = I.nb;
     constexpr int CAP = PPT * NT;
+    static_assert(NT >= MAX_BINS, "the gather takes one window bin per thread");
     const Lds L = carve(smem, carve_cap, nb);
     const int ix = c % I.nx, iy = c / I.nx;
     const bool per_x = I.face_kind[0] == 2, per_y = I.face_kind[2] == 2;
@@ -634,36 +637,40 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
         }
         return code;
     };
-    long long tmark = clock64();
+    // phase time stamps go to LDS (no stall on a global read-modify-write in
+    // the timed code); the durations are added to the record at the end
+    if (dg && tid == 0) {
+        for (int k = 0; k < 15; ++k) L.tst[k] = 0;
+        L.tst[15] = clock64();
+    }
     auto mark = [&](int k) {
-        if (dg && tid == 0) {
-            const long long t = clock64();
-            dg[NDIAG_STEP + k] += (double)(t - tmark);
-            tmark = t;
-        }
+        if (dg && tid == 0) L.tst[k] = clock64();
     };
     Parts<real, DIM, PPT> P;
 
     if (!gs.ready) {
-    // per-cell inputs of the lane-0 sections, loaded while the gather runs
+    // ---- gather: window bins of the neighbours, then far arrivals.  All
+    // global loads of this part are issued before any of them is waited for:
+    // the per-cell inputs of the lane-0 sections, the far-list length and the
+    // neighbours' bin offsets (nb <= 256 bins: one per thread).
+    double pv = 0.0;
     if (tid < 41) {
-        double v = 0.0;
         if (tid < 13) {
-            if (I.jmom_mode == 1) v = I.avgs[(size_t)tid * I.ncell + c];
+            if (I.jmom_mode == 1) pv = I.avgs[(size_t)tid * I.ncell + c];
         } else if (tid < 26) {
-            v = I.avg[(size_t)(tid - 13) * I.ncell + c];
+            pv = I.avg[(size_t)(tid - 13) * I.ncell + c];
         } else if (tid < 39) {
-            v = I.mom[(size_t)(tid - 26) * I.ncell + c];
+            pv = I.mom[(size_t)(tid - 26) * I.ncell + c];
         } else {
-            v = tid == 39 ? I.pcur[c] : I.pprev[c];
+            pv = tid == 39 ? I.pcur[c] : I.pprev[c];
         }
-        L.pre[tid] = v;
     }
-
-    // ---- gather: window bins of the neighbours, then far arrivals
+    const int nfar_all = I.far_n[cur];
     {
         const uint32_t* tin = I.tab[cur];
-        for (int b = tid; b < nb; b += NT) {
+        const int b = tid;
+        uint32_t len = 0, base = 0;
+        if (b < nb) {
             const int oy = b / I.nbx - I.Ky, ox = b % I.nbx - I.Kx;
             int sy = iy + oy, sx = ix + ox;
             bool ok = true;
@@ -675,7 +682,6 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             } else {
                 sx = 0;
             }
-            uint32_t len = 0, base = 0;
             if (ok) {
                 const int s = sy * I.nx + sx;
                 const uint32_t* t = tin + (size_t)s * (nb + 1);
@@ -683,13 +689,15 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                 len = a1 - a0;
                 base = (uint32_t)s * (uint32_t)I.cap + a0;
             }
+        }
+        if (tid < 41) L.pre[tid] = pv;
+        if (b < nb) {
             L.run_pre[b] = len;
             L.run_src[b] = base;
         }
         if (tid == 0) L.fcount[0] = 0u;
         __syncthreads();
         wave0_scan(L.run_pre, nb, tid);
-        const int nfar_all = I.far_n[cur];
         if (nfar_all > 0) {
             const uint32_t* fm = I.far_meta[cur];
             for (int e = tid; e < nfar_all && e < I.far_cap; e += NT)
@@ -737,7 +745,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     gs.err = errbits;
     gs.ready = true;
     }
-    const int nfc = gs.nfc, nwin = gs.nwin;
+    const int nfc = gs.nfc;
     int n0 = gs.n0;
     errbits |= gs.err;
     if (can_defer && n0 <= I.max_ppc) {
@@ -752,16 +760,16 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
         errbits |= ERR_CAPACITY;
         n0 = I.max_ppc < CAP ? I.max_ppc : CAP;
     }
-    for (int j = tid; j < nwin; j += NT) {
-        int lo = 0, hi = nb - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (L.run_pre[mid] <= (uint32_t)j) lo = mid;
-            else hi = mid - 1;
+    // gather map: each run (one bin of one neighbour) written by a group of
+    // 4 threads, interleaved over the run's particles
+    for (int t = tid; t < 4 * nb; t += NT) {
+        const int b = t >> 2;
+        const uint32_t len = L.run_pre[b + 1] - L.run_pre[b];
+        const uint32_t dst0 = L.run_dst[b], src0 = L.run_src[b];
+        for (uint32_t off = (uint32_t)(t & 3); off < len; off += 4) {
+            const uint32_t dst = dst0 + off;
+            if ((int)dst < n0) L.srcmap[dst] = src0 + off;
         }
-        const uint32_t off = (uint32_t)j - L.run_pre[lo];
-        const uint32_t dst = L.run_dst[lo] + off;
-        if ((int)dst < n0) L.srcmap[dst] = L.run_src[lo] + off;
     }
     for (int k = tid; k < nfc; k += NT)
         if ((int)L.fpos[k] < n0) L.srcmap[L.fpos[k]] = FARBIT | L.fent[k];
@@ -1260,6 +1268,16 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) e |= __shfl_xor(e, o, 64);
         if ((tid & 63) == 0) atomicOr(&I.ctl[CTL_ERR], (int)e);
+    }
+    if (dg && tid == 0) {
+        long long prev = L.tst[15];
+        for (int k = 0; k < 15; ++k) {
+            const long long t = L.tst[k];
+            if (t != 0) {
+                dg[NDIAG_STEP + k] += (double)(t - prev);
+                prev = t;
+            }
+        }
     }
     return 0;
 }

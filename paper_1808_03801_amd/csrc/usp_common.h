@@ -118,6 +118,7 @@ inline size_t lds_bytes(int cap, int nb)
     b += r16((size_t)PSB * 6 * 8);              // Gram-sum staging
     b += r16(32 * 8);                           // pending moments
     b += r16(48 * 8);                           // per-cell inputs
+    b += r16(16 * 8);                           // phase time stamps
     b += r16(256) + r16(32 * 8);                // cell scalars, moments
     return b;
 }

@@ -504,6 +504,7 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
     h.Ky = w.Ky;
     h.nbx = 2 * w.Kx + 1;
     h.nb = (2 * w.Ky + 1) * h.nbx;
+    if (h.nb > MAX_BINS) return fail(ctx, USP_EINVAL, "sort window larger than 256 bins");
     h.cap = (nm->max_ppc + 63) / 64 * 64;
 
     const size_t ncell = (size_t)h.ncell;
