@@ -303,7 +303,9 @@ __device__ __forceinline__ void psi5(double c0, double c1, double c2, const doub
 // Returns the destination cell.
 // ---------------------------------------------------------------------------
 // Wall-to-wall trace of a particle that leaves the domain during the step
-// (double precision); rare, so kept out of line.
+// (double precision).  Inlined: an out-of-line call makes the caller keep its
+// particle registers clear of the call-clobbered ones, which costs more
+// registers than the inlined trace itself.
 template <typename real>
 struct Flight {
     real px, py, c0, c1, c2;
@@ -312,7 +314,7 @@ struct Flight {
 
 // Values in, values out: no address of the caller's registers escapes.
 template <typename real, int DIM>
-__device__ __noinline__ Flight<real> wall_trace(const InstDev& I, real px, real py, real c0,
+__device__ __forceinline__ Flight<real> wall_trace(const InstDev& I, real px, real py, real c0,
                                                 real c1, real c2, int src_cell, int slot,
                                                 uint32_t step)
 {

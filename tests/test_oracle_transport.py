@@ -71,3 +71,42 @@ def test_sp_limit_viscosity_matches_the_splitting_closed_form(dto):
     assert abs(r - ref) < max(0.15 * ref, 0.05), (r, ref)
     # and is far from the USP value at these steps
     assert r < 0.6
+
+
+def _poiseuille_mu_eff(dt_over_tau, pne, seed, ncell=30, ppc=200, Kn=0.05, umax=100.0,
+                       steps=1500, warm=300):
+    """Body-force driven channel: the time-averaged shear stress against the
+    local velocity gradient of the averaged profile (a fitted parabola) in the
+    core, mu_eff = -sum(sigma du/dy) / sum((du/dy)^2) / mu(T)"""
+    gas = P.Gas(omega=0.81)
+    n0, rho0, lam0, tau0 = P.standard_state(gas, 273.0)
+    H = lam0 / Kn
+    dpdx = 8.0 * gas.mu(273.0) * umax / (H * H)
+    pb = P.poiseuille_1d(Kn=Kn, dpdx=dpdx, ncell=ncell, ppc=ppc, dt_over_tau=dt_over_tau,
+                         seed=seed, precision=64)
+    y = (np.arange(ncell) + 0.5) * H / ncell
+    iu = np.zeros((ncell, 3))
+    iu[:, 0] = 4.0 * umax * y * (H - y) / H ** 2 + 0.1 * umax
+    pb = pb.replace(init_u=iu, n_avg=100, pne_mode=P.PNE_FIXED, pne_fixed=pne)
+    o = O.Oracle(pb)
+    acc = np.zeros((ncell, 18))
+    for k in range(steps):
+        o.step(1)
+        assert o.error == 0
+        if k >= warm:
+            acc += o.fields(0)
+    f = acc / (steps - warm)
+    core = slice(ncell // 6, ncell - ncell // 6)
+    c2, c1, _ = np.polyfit(y[core], f[core, 2], 2)
+    dudy = 2.0 * c2 * y[core] + c1
+    mu_fit = -np.sum(f[core, 10] * dudy) / np.sum(dudy * dudy)
+    return mu_fit / gas.mu(f[core, 5].mean())
+
+
+def test_poiseuille_stress_follows_the_local_shear_at_large_dt():
+    """the same viscosity in a curved (body-force driven) profile at dt = 5
+    tau_c: USP within 10 % of mu, the SP-ESBGK limit at the closed form"""
+    usp = np.mean([_poiseuille_mu_eff(5.0, 1.0, s) for s in (1, 2)])
+    assert abs(usp - 1.0) < 0.1, usp
+    sp = np.mean([_poiseuille_mu_eff(5.0, 0.0, s) for s in (1, 2)])
+    assert abs(sp - _sp_closed_form(5.0)) < 0.05, sp
