@@ -4,8 +4,11 @@
 // live in registers: particle j of the cell is held by thread j % 256 in
 // register slot j / 256 (PPT slots per thread, fully unrolled), so every
 // per-particle phase runs without LDS traffic and with PPT independent
-// instruction streams per thread.  LDS holds only small tables: the gather
-// map, bin tile counts, histograms and reduction scratch.
+// instruction streams per thread.  LDS holds only tables: the gather map, bin
+// tile counts, the rank histogram, reduction scratch, the staging of the Gram
+// sums of added batches and the cell scalars.  PPT is a template parameter
+// (1, 2, 4, 6 or 8); the 4|6 kernel reruns a cell that needs more than 1024
+// slots with 6 per thread in the same workgroup.
 //
 // Phases for one cell (mode bits select them):
 //   gather    read the cell's arrivals from the neighbours' bins in canonical
@@ -30,6 +33,7 @@ namespace usp {
 
 constexpr int MAX_NW = 4;  // waves per workgroup (256 threads)
 constexpr int FAR_BIN = 0xFFFF;
+constexpr uint32_t FAR_PENDING = 0xFFFEu;  // leaves the sort window; far list not yet written
 constexpr uint32_t FARBIT = 0x80000000u;
 
 // fate codes
@@ -38,7 +42,7 @@ enum { FT_KEEP = 0, FT_REASSIGN = 1, FT_DELETE = 2, FT_SEL = 3, FT_EMPTY = 4 };
 struct Lds {
     uint32_t* srcmap;  // [cap] source index of each gathered position
     uint16_t* tiles;   // [cap / 64][nb]
-    uint32_t* hist;    // [256]
+    uint32_t* hist;    // [KTH_BINS]
     uint32_t* wtot;    // [64] per-wave scan totals
     double* red;       // [NW][24]
     uint32_t* run_pre;
@@ -74,7 +78,7 @@ __device__ __forceinline__ Lds carve(unsigned char* sm, int cap, int nb)
     };
     L.srcmap = (uint32_t*)take((size_t)cap * 4);
     L.tiles = (uint16_t*)take((size_t)(cap / 64) * nb * 2);
-    L.hist = (uint32_t*)take(256 * 4);
+    L.hist = (uint32_t*)take((size_t)KTH_BINS * 4);
     L.wtot = (uint32_t*)take(64 * 4);
     L.red = (double*)take((size_t)MAX_NW * 24 * 8);
     L.run_pre = (uint32_t*)take((size_t)(nb + 1) * 4);
@@ -489,64 +493,68 @@ __device__ __forceinline__ int resample_one(const InstDev& I, int cell, int slot
     return fb;
 }
 
-// k-th smallest (1-based) rank key among the selected particles: 4 passes of
-// an 8-bit LDS histogram, most significant digit first
+// k-th smallest (1-based) rank key among the selected particles.  The keys
+// are 21 random bits over the 11-bit slot, so an 11-bit histogram of the top
+// bits leaves about nsel / 2048 keys in the bucket that holds the k-th; those
+// are collected (into the gather map, free during the relaxation) and ranked
+// exactly by wave 0.  Keys are distinct (they end in the slot).
 template <int NT, typename real, int DIM, int PPT>
 __device__ uint32_t kth_key_r(const Parts<real, DIM, PPT>& P, const Lds& L, int kth, int nuse,
                               int tid)
 {
-    uint32_t prefix = 0;
-    int rem = kth;
-#pragma unroll 1
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        for (int b = tid; b < 256; b += NT) L.hist[b] = 0u;
-        __syncthreads();
-        const uint32_t hmask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+    constexpr int NB = KTH_BINS;
+    for (int b = tid; b < NB; b += NT) L.hist[b] = 0u;
+    if (tid == 0) L.fcount[1] = 0u;
+    __syncthreads();
 #pragma unroll
-        for (int k = 0; k < PPT; ++k)
-            if (k * NT < nuse && fate(P, k) == FT_SEL && (P.key[k] & hmask) == prefix)
-                atomicAdd(&L.hist[(P.key[k] >> shift) & 255u], 1u);
-        __syncthreads();
-        if (tid < 64) {
-            uint32_t c4[4], s = 0;
+    for (int k = 0; k < PPT; ++k)
+        if (k * NT < nuse && fate(P, k) == FT_SEL) atomicAdd(&L.hist[P.key[k] >> 21], 1u);
+    __syncthreads();
+    if (tid < 64) {
+        // lane l owns buckets [32 l, 32 l + 32)
+        uint32_t s = 0;
+#pragma unroll 8
+        for (int q = 0; q < NB / 64; ++q) s += L.hist[tid * (NB / 64) + q];
+        uint32_t incl = s;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                c4[q] = L.hist[4 * tid + q];
-                s += c4[q];
-            }
-            uint32_t incl = s;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t t = __shfl_up(incl, o, 64);
-                if (tid >= o) incl += t;
-            }
-            uint32_t run = incl - s;
-            int found = -1;
-            uint32_t before = 0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (found < 0 && run < (uint32_t)rem && run + c4[q] >= (uint32_t)rem) {
-                    found = 4 * tid + q;
-                    before = run;
-                }
-                run += c4[q];
-            }
-            const uint64_t m = __ballot(found >= 0);
-            const int src = m ? __ffsll((unsigned long long)m) - 1 : 0;
-            const int fb = __builtin_amdgcn_readlane(found, src);
-            const int bb = __builtin_amdgcn_readlane((int)before, src);
-            if (tid == 0) {
-                L.wtot[62] = (uint32_t)fb;
-                L.wtot[63] = (uint32_t)bb;
-            }
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o, 64);
+            if (tid >= o) incl += t;
         }
-        __syncthreads();
-        const uint32_t digit = L.wtot[62] & 255u;
-        rem -= (int)L.wtot[63];
-        prefix |= digit << shift;
-        __syncthreads();
+        const uint32_t excl = incl - s;
+        const bool here = excl < (uint32_t)kth && incl >= (uint32_t)kth;
+        if (here) {
+            uint32_t run = excl;
+            int q = 0;
+            for (; q < NB / 64; ++q) {
+                const uint32_t h = L.hist[tid * (NB / 64) + q];
+                if (run + h >= (uint32_t)kth) break;
+                run += h;
+            }
+            L.wtot[62] = (uint32_t)(tid * (NB / 64) + q);  // bucket of the k-th
+            L.wtot[63] = run;                              // keys below that bucket
+        }
     }
-    return prefix;
+    __syncthreads();
+    const uint32_t bucket = L.wtot[62];
+    const int rem = kth - (int)L.wtot[63];
+    uint32_t* cand = L.srcmap;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+        if (k * NT < nuse && fate(P, k) == FT_SEL && (P.key[k] >> 21) == bucket)
+            cand[atomicAdd(&L.fcount[1], 1u)] = P.key[k];
+    __syncthreads();
+    if (tid < 64) {
+        const int m = (int)L.fcount[1];
+        for (int i = tid; i < m; i += 64) {
+            const uint32_t ki = cand[i];
+            int r = 0;
+            for (int j = 0; j < m; ++j) r += cand[j] < ki ? 1 : 0;
+            if (r == rem - 1) L.wtot[61] = ki;
+        }
+    }
+    __syncthreads();
+    return L.wtot[61];
 }
 
 // Cell scalars, computed by wave 0: lane 0 derives f from the centred
@@ -930,9 +938,9 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             // conservation of the cell's mass, momentum and energy
             double WrOut = 0.0, s2Out = 0.0;
             if (I.conserve_mode == 0) {
-                double cs[8];
+                double cs[9];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) cs[q] = 0.0;
+                for (int q = 0; q < 9; ++q) cs[q] = 0.0;
                 const int npu = uni(nphys);
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
@@ -951,6 +959,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                         cs[5] += c0;
                         cs[6] += c1;
                         cs[7] += c2;
+                        cs[8] += c0 * c0 + c1 * c1 + c2 * c2;
                     }
                 }
                 bsum<NT>(cs, L.red, tid);
@@ -970,17 +979,10 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                             a[q] = (Ms[27 + q] - cs[1 + q]) / MR;
                             cb[q] = cs[5 + q] / nusp;
                         }
-                        double dd[1] = {0.0};
-#pragma unroll
-                        for (int k = 0; k < PPT; ++k)
-                            if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
-                                const double e0 = (double)P.c0[k] - cb[0];
-                                const double e1 = (double)P.c1[k] - cb[1];
-                                const double e2 = (double)P.c2[k] - cb[2];
-                                dd[0] += e0 * e0 + e1 * e1 + e2 * e2;
-                            }
-                        bsum<NT>(dd, L.red, tid);
-                        const double D = dd[0];
+                        // sum over the reassigned of |c - cb|^2, from the same
+                        // pass: sum |c|^2 - |sum c|^2 / N_usp (FP64)
+                        const double D = cs[8] - nusp * (cb[0] * cb[0] + cb[1] * cb[1] +
+                                                         cb[2] * cb[2]);
                         const double a2 = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
                         double sc = 1.0;
                         if (nusp >= 2 && D > 0.0) {
@@ -1096,7 +1098,9 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
 
     if (mode & MODE_MOVE) {
         const uint32_t mstep = (mode & MODE_RELAX) ? step + 1 : step;
-        // cell scalars of f^{n+1} (or f^n when no relaxation ran) for step 2
+        // cell scalars of f^{n+1} (or f^n when no relaxation ran) for step 2,
+        // derived by wave 0 while every wave starts step 3 on the particles
+        // already present (which does not need them)
         if (tid < 64) {
             const bool have = (mode & (MODE_RELAX | MODE_MOMENTS)) != 0;
             double m[NMOM], A[NMOM];
@@ -1111,6 +1115,42 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                                          I.jmom_mode == 1 && (ns_after > 0 || I.avg_init), tid);
             if (tid == 0) f = fw;
         }
+        // step 3 for particles at physical positions [lo, hi): advect, walls,
+        // destination bin; a particle leaving the sort window is marked and
+        // goes to the far list only once the cell can no longer be handed on
+        int clamps = 0;
+        auto move = [&](int lo, int hi, bool reset) {
+            const int hiu = uni(hi);
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int j = k * NT + tid;
+                if (k * NT < hiu && j >= lo && j < hi && fate(P, k) <= FT_REASSIGN) {
+                    real px = DIM == 2 ? P.x[k] : (real)0;
+                    real py = P.y[k];
+                    real v0 = P.c0[k], v1 = P.c1[k], v2 = P.c2[k];
+                    const int slot = (int)(P.st[k] >> 8);
+                    const int d =
+                        advect<real, DIM>(I, px, py, v0, v1, v2, c, slot, mstep, &clamps);
+                    if (DIM == 2) P.x[k] = px;
+                    P.y[k] = py;
+                    P.c0[k] = v0;
+                    P.c1[k] = v1;
+                    P.c2[k] = v2;
+                    const int dy_ = DIM == 2 ? d / I.nx : d;
+                    const int dx_ = DIM == 2 ? d - dy_ * I.nx : 0;
+                    const int oy = min_image(iy - dy_, I.ny, per_y);
+                    const int ox = DIM == 2 ? min_image(ix - dx_, I.nx, per_x) : 0;
+                    if (oy < -I.Ky || oy > I.Ky || ox < -I.Kx || ox > I.Kx)
+                        P.key[k] = FAR_PENDING;
+                    else
+                        P.key[k] = (uint32_t)((oy + I.Ky) * I.nbx + (ox + I.Kx));
+                } else if (reset) {
+                    P.key[k] = FAR_BIN;
+                }
+            }
+        };
+        const int nphys0 = nphys;
+        move(0, nphys0, true);
         __syncthreads();
         const double P2 = (mode & MODE_RELAX) ? L.pre[39] : L.pre[40];
         double mc2 = __builtin_inf();
@@ -1122,49 +1162,35 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
         nphys += n2;
         nlog += n2;
         mark(10);
-        // step 3: advect, walls, destination bin (or far list)
-        int clamps = 0;
-        const int npu2 = uni(nphys);
+        if (n2 > 0) move(nphys0, nphys, false);
+        // far movers: appended now, with their destination cell and offsets
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            uint32_t b = FAR_BIN;
-            if (k * NT < npu2 && fate(P, k) <= FT_REASSIGN) {
-                real px = DIM == 2 ? P.x[k] : (real)0;
-                real py = P.y[k];
-                real v0 = P.c0[k], v1 = P.c1[k], v2 = P.c2[k];
-                const int slot = (int)(P.st[k] >> 8);
-                const int d = advect<real, DIM>(I, px, py, v0, v1, v2, c, slot, mstep, &clamps);
-                if (DIM == 2) P.x[k] = px;
-                P.y[k] = py;
-                P.c0[k] = v0;
-                P.c1[k] = v1;
-                P.c2[k] = v2;
+            if (P.key[k] == FAR_PENDING) {
+                const int d = cell_index<real, DIM>(I, DIM == 2 ? P.x[k] : (real)0, P.y[k]);
                 const int dy_ = DIM == 2 ? d / I.nx : d;
                 const int dx_ = DIM == 2 ? d - dy_ * I.nx : 0;
                 const int oy = min_image(iy - dy_, I.ny, per_y);
                 const int ox = DIM == 2 ? min_image(ix - dx_, I.nx, per_x) : 0;
-                if (oy < -I.Ky || oy > I.Ky || ox < -I.Kx || ox > I.Kx) {
-                    const int e = atomicAdd(&I.far_n[1 - cur], 1);
-                    if (e < I.far_cap) {
-                        uint32_t* fm = I.far_meta[1 - cur] + 3 * (size_t)e;
-                        fm[0] = (uint32_t)d;
-                        fm[1] = ((uint32_t)(oy + 32768) << 16) | (uint32_t)(ox + 32768);
-                        fm[2] = (uint32_t)slot;
-                        real* const* fo = (real* const*)I.far_pc[1 - cur];
-                        if (DIM == 2) fo[0][e] = px;
-                        fo[1][e] = py;
-                        fo[2][e] = P.c0[k];
-                        fo[3][e] = P.c1[k];
-                        fo[4][e] = P.c2[k];
-                        fo[5][e] = P.w[k];
-                    } else {
-                        errbits |= ERR_WINDOW;
-                    }
+                const int slot = (int)(P.st[k] >> 8);
+                const int e = atomicAdd(&I.far_n[1 - cur], 1);
+                if (e < I.far_cap) {
+                    uint32_t* fm = I.far_meta[1 - cur] + 3 * (size_t)e;
+                    fm[0] = (uint32_t)d;
+                    fm[1] = ((uint32_t)(oy + 32768) << 16) | (uint32_t)(ox + 32768);
+                    fm[2] = (uint32_t)slot;
+                    real* const* fo = (real* const*)I.far_pc[1 - cur];
+                    if (DIM == 2) fo[0][e] = P.x[k];
+                    fo[1][e] = P.y[k];
+                    fo[2][e] = P.c0[k];
+                    fo[3][e] = P.c1[k];
+                    fo[4][e] = P.c2[k];
+                    fo[5][e] = P.w[k];
                 } else {
-                    b = (uint32_t)((oy + I.Ky) * I.nbx + (ox + I.Kx));
+                    errbits |= ERR_WINDOW;
                 }
+                P.key[k] = FAR_BIN;
             }
-            P.key[k] = b;
         }
         mark(11);
         // stable ranks by bin over physical positions (tiles of 64)
@@ -1175,6 +1201,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
         // lanes of a wave that share a bin, found bit by bit of the bin
         // index (one ballot per bit instead of one per distinct bin)
         const int nbits = 32 - __clz(nb - 1 > 0 ? nb - 1 : 1);
+        const int npu_t = uni(nphys);
         uint32_t rank[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -1183,7 +1210,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             const int b = (int)P.key[k];
             const int tile = j >> 6;
             rank[k] = 0;
-            if (k * NT >= npu2) continue;
+            if (k * NT >= npu_t) continue;
             uint64_t peers = __ballot(act);
 #pragma unroll
             for (int bit = 0; bit < 8; ++bit) {

@@ -13,6 +13,7 @@ constexpr int MAX_BINS = 256;
 constexpr int MAX_PPC = 2048;
 constexpr int FAR_LDS = 128;  // far arrivals one cell can take per step
 constexpr int PSB = 256;      // added particles per chunk of the batch-order Gram sums
+constexpr int KTH_BINS = 2048;  // buckets of the rank-threshold histogram (top 11 key bits)
 
 // control words of an instance (device memory)
 enum { CTL_CUR = 0, CTL_STEP = 1, CTL_NSAMP = 2, CTL_ERR = 3, CTL_N = 4 };
@@ -110,7 +111,7 @@ inline size_t lds_bytes(int cap, int nb)
     size_t b = 0;
     b += r16((size_t)cap * 4);                  // gather map
     b += r16((size_t)(cap / 64) * nb * 2);      // bin tile counts
-    b += r16(256 * 4) + r16(64 * 4);            // histogram, scan totals
+    b += r16((size_t)KTH_BINS * 4) + r16(64 * 4);  // histogram, scan totals
     b += r16(4 * 24 * 8);                       // reductions (4 waves)
     b += 4 * r16((size_t)(nb + 1) * 4);         // runs, bin offsets
     b += r16((size_t)FAR_LDS * 8) + 3 * r16((size_t)FAR_LDS * 4) + r16(16);  // far arrivals

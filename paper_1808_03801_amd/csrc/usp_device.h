@@ -403,6 +403,20 @@ __device__ __forceinline__ Flight<real> wall_trace(const InstDev& I, real px, re
     return fo;
 }
 
+// cell of a position inside the domain (indices clamped to the grid)
+template <typename real, int DIM>
+__device__ __forceinline__ int cell_index(const InstDev& I, real px, real py)
+{
+    int iy = (int)floor(((double)py - I.y0) * I.inv_dy);
+    iy = iy < 0 ? 0 : (iy > I.ny - 1 ? I.ny - 1 : iy);
+    int ix = 0;
+    if (DIM == 2) {
+        ix = (int)floor(((double)px - I.x0) * I.inv_dx);
+        ix = ix < 0 ? 0 : (ix > I.nx - 1 ? I.nx - 1 : ix);
+    }
+    return iy * I.nx + ix;
+}
+
 template <typename real, int DIM>
 __device__ __forceinline__ int advect(const InstDev& I, real& px, real& py, real& c0, real& c1,
                                       real& c2, int src_cell, int slot, uint32_t step, int* clamp)
@@ -428,14 +442,7 @@ __device__ __forceinline__ int advect(const InstDev& I, real& px, real& py, real
     if (I.accel[0] != 0.0) c0 = c0 + (real)(I.accel[0] * I.dt);
     if (I.accel[1] != 0.0) c1 = c1 + (real)(I.accel[1] * I.dt);
     if (I.accel[2] != 0.0) c2 = c2 + (real)(I.accel[2] * I.dt);
-    int iy = (int)floor(((double)py - I.y0) * I.inv_dy);
-    iy = iy < 0 ? 0 : (iy > I.ny - 1 ? I.ny - 1 : iy);
-    int ix = 0;
-    if (DIM == 2) {
-        ix = (int)floor(((double)px - I.x0) * I.inv_dx);
-        ix = ix < 0 ? 0 : (ix > I.nx - 1 ? I.nx - 1 : ix);
-    }
-    return iy * I.nx + ix;
+    return cell_index<real, DIM>(I, px, py);
 }
 
 
