@@ -51,7 +51,7 @@ typedef enum {
     USP_ENOLIB = -8     /* built without device support */
 } usp_status;
 
-enum { USP_BC_DIFFUSE = 0, USP_BC_SPECULAR = 1, USP_BC_PERIODIC = 2 };
+enum { USP_BC_DIFFUSE = 0, USP_BC_SPECULAR = 1, USP_BC_PERIODIC = 2, USP_BC_OPEN = 3 };
 enum { USP_PNE_FIXED = 0, USP_PNE_GLL_INST = 1, USP_PNE_GLL_AVG = 2 };
 enum { USP_WEIGHT_CONSISTENT = 0, USP_WEIGHT_LITERAL = 1 };
 enum { USP_CONSERVE_FULL = 0, USP_CONSERVE_NONE = 1 };
@@ -64,23 +64,45 @@ typedef struct {
 } usp_gas;
 
 /* A face of the domain: kind USP_BC_*, wall temperature T and wall velocity u
- * (diffuse faces; full accommodation). */
+ * (diffuse faces; full accommodation).
+ *
+ * Open faces (USP_BC_OPEN; the Sod tube's open ends of Section 4.3 and the
+ * reservoirs of the slit of Section 4.5): the face borders a reservoir of gas
+ * with number density n (1/m^3), temperature T and velocity u, whose
+ * component normal to the face must be 0.  A particle that reaches the face
+ * leaves the domain; every step, the reservoir's molecules that cross the
+ * face enter: per boundary cell a stochastically rounded n sqrt(kT/(2 pi m))
+ * A dt / Np of them (A = the cell's share of the face: unit area in 1-D, dx or
+ * dy per unit depth in 2-D), each at a uniform point of that share and a
+ * uniform time of the step, with a velocity from the flux-weighted half-range
+ * Maxwellian, weight 1.  On the part of a face whose tangential coordinate
+ * (2-D: x on a y face, y on an x face; the cell centre decides) is >= split,
+ * the reservoir has density n_b and temperature T_b instead (a face that
+ * borders two chambers); split = +inf for a uniform face.  Open faces cannot
+ * be combined with a body acceleration. */
 typedef struct {
     int kind;
     double T;
     double u[3];
+    double n, split, n_b, T_b;
 } usp_face;
 
 /* Geometry.  Domain [x0, x1] x [y0, y1] with nx * ny uniform cells of widths
  * dx, dy (inv_dx = 1/dx, inv_dy = 1/dy supplied so that every solver uses the
  * same numbers); vcell = cell volume (per unit depth / area in 2-D / 1-D).
- * face[0..3] = x-lo, x-hi, y-lo, y-hi (x faces are unused in 1-D).
- * accel = uniform body acceleration (the Poiseuille drive), m/s^2. */
+ * face[0..3] = x-lo, x-hi, y-lo, y-hi (x faces are unused in 1-D; a periodic
+ * face needs a periodic opposite face).  accel = uniform body acceleration
+ * (the Poiseuille drive), m/s^2.  plate != 0 (2-D only): a thin diffuse wall
+ * at rest and at temperature plate_T on the line x = plate_x (strictly inside
+ * the domain) for plate_ylo <= y <= plate_yhi, reflecting on both sides (the
+ * wall between the two chambers of the slit, Section 4.5). */
 typedef struct {
     int dim, nx, ny;
     double x0, x1, y0, y1, dx, dy, inv_dx, inv_dy, vcell;
     usp_face face[4];
     double accel[3];
+    int plate;
+    double plate_x, plate_ylo, plate_yhi, plate_T;
 } usp_problem;
 
 /* Numerics.  dt: time step (s); Np: real molecules per unit weight; r_p:

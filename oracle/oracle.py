@@ -21,7 +21,7 @@ NDIAG = 32
 DIAG = dict(n_in=0, n4=1, n_sel=2, n_usp=3, n_del=4, n7=5, n_out=6, n2=7, s_sel=8, p_sel=9,
             flags=10, chol_fb=11, M0=12, P0x=13, P0y=14, P0z=15, E0=16, M1=17, P1x=18, P1y=19,
             P1z=20, E1=21, clamp=22, marg_sel=23, marg_round=24, marg_cnt=25, Wr=26, s2=27,
-            marg_cnt2=28)
+            marg_cnt2=28, n_inj=29, n_gone=30)
 
 
 class Config(C.Structure):
@@ -40,6 +40,10 @@ class Config(C.Structure):
         ("precision", C.c_int), ("weight_mode", C.c_int), ("conserve_mode", C.c_int),
         ("max_ppc", C.c_int), ("jmom_mode", C.c_int), ("spawn_projection", C.c_int),
         ("seed_lo", C.c_uint32), ("seed_hi", C.c_uint32), ("avg_init", C.c_int),
+        ("face_n", C.c_double * 4), ("face_split", C.c_double * 4), ("face_nb", C.c_double * 4),
+        ("face_Tb", C.c_double * 4),
+        ("plate", C.c_int), ("plate_x", C.c_double), ("plate_ylo", C.c_double),
+        ("plate_yhi", C.c_double), ("plate_T", C.c_double),
     ]
 
 
@@ -78,6 +82,8 @@ def lib():
         L.uspo_test_fields.argtypes = [C.POINTER(Config), dp, C.c_int, dp, dp]
         L.uspo_test_advect.argtypes = [C.POINTER(Config), dp, C.c_int, C.c_int, C.c_int]
         L.uspo_test_pne.argtypes = [C.POINTER(Config), dp, dp]
+        L.uspo_test_inject.argtypes = [C.POINTER(Config), C.c_int, C.c_int, C.c_int, C.c_int, dp,
+                                       C.c_int]
         _lib = L
     return _lib
 
@@ -102,6 +108,9 @@ def make_config(pb) -> Config:
         g.face_T[i] = f.T
         for k in range(3):
             g.face_u[3 * i + k] = f.u[k]
+        g.face_n[i], g.face_split[i], g.face_nb[i], g.face_Tb[i] = f.n, f.split, f.n_b, f.T_b
+    g.plate, g.plate_x, g.plate_ylo, g.plate_yhi, g.plate_T = (pb.plate, pb.plate_x, pb.plate_ylo,
+                                                              pb.plate_yhi, pb.plate_T)
     for k in range(3):
         g.accel[k] = pb.accel[k]
     g.dt, g.Np, g.r_p, g.Kn_c, g.pne_fixed = pb.dt, pb.Np, pb.r_p, pb.Kn_c, pb.pne_fixed
@@ -246,6 +255,17 @@ def advect(pb, part6, src_cell, slot, step):
     r = np.ascontiguousarray(part6, dtype=np.float64).copy()
     d = lib().uspo_test_advect(C.byref(cfg), _dp(r), src_cell, slot, step)
     return d, r
+
+
+def inject(pb, step, cell, face, slot0=0, max_out=4096):
+    """particles entering `cell` through open face `face` at `step`:
+    [n, 7] = x, y, cx, cy, cz, w, destination cell (-1: left again)"""
+    cfg = make_config(pb)
+    out = np.zeros((max_out, 7))
+    n = lib().uspo_test_inject(C.byref(cfg), step, cell, face, slot0, _dp(out), max_out)
+    if n < 0:
+        raise ValueError("bad configuration")
+    return out[:min(n, max_out)]
 
 
 def pne_of(pb, mom):

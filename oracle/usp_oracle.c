@@ -55,7 +55,10 @@ enum {
     PUR_SPAWN_VEL = 5,
     PUR_WALL = 6,
     PUR_SELECT = 7,
-    PUR_RESAMPLE = 8
+    PUR_RESAMPLE = 8,
+    PUR_INJECT_CNT = 9,
+    PUR_INJECT = 10,
+    PUR_INJECT_POS = 11
 };
 
 /* Philox4x32 with 10 rounds.  Round: multiply words 0 and 2 by the two
@@ -141,7 +144,7 @@ static void pl_push(plist* l, part q)
 enum {
     D_NIN = 0, D_N4, D_NSEL, D_NUSP, D_NDEL, D_N7, D_NOUT, D_N2, D_SSEL, D_PSEL, D_FLAGS,
     D_CHOLFB, D_M0, D_P0X, D_P0Y, D_P0Z, D_E0, D_M1, D_P1X, D_P1Y, D_P1Z, D_E1, D_CLAMP,
-    D_MARG_SEL, D_MARG_ROUND, D_MARG_CNT, D_WR, D_S2, D_MARG_CNT2
+    D_MARG_SEL, D_MARG_ROUND, D_MARG_CNT, D_WR, D_S2, D_MARG_CNT2, D_NINJ, D_NGONE
 };
 enum { F_SKIP = 1, F_FAILMASS = 2, F_FAILENERGY = 4, F_NOUSP = 8 };
 
@@ -531,15 +534,122 @@ static int cell_of(const uspo_config* g, double x, double y)
     return iy * g->nx + ix;
 }
 
-/* Moves one particle for dt.  A particle that stays inside moves by one fused
- * multiply-add in the state precision.  One that would leave is traced wall
- * to wall in double precision: specular faces mirror the normal velocity,
- * periodic faces wrap, diffuse faces re-emit it with full accommodation
- * (normal speed sqrt(-2 theta_w ln u), tangential wall velocity plus a
- * Maxwellian at the wall temperature) for the rest of the step.  After 16 hits
- * the particle is left where it is (counted).  A body acceleration (the
- * Poiseuille drive) adds a dt to the velocity afterwards.  Returns the new
- * cell; *clamped counts the capped traces. */
+/* Diffuse re-emission with full accommodation from a wall or an open face:
+ * normal speed sqrt(-2 theta ln u0) away from the surface (side sd = 1 means
+ * the surface faces the -axis direction), tangential velocity uw plus a
+ * Maxwellian at theta from the Box-Muller pair of (u1, u2). */
+static void reemit(double vel[3], int axis, int sd, double theta, const double uw[3], double u0,
+                   double u1, double u2)
+{
+    double vn = sqrt(-2.0 * theta * log(u0));
+    double rad = sqrt(-2.0 * log(u1));
+    double z0 = rad * cos(2.0 * M_PI * u2), z1 = rad * sin(2.0 * M_PI * u2);
+    int ta = axis == 0 ? 1 : 0, tb = 2;
+    vel[axis] = sd ? -vn : vn;
+    vel[ta] = uw[ta] + sqrt(theta) * z0;
+    vel[tb] = uw[tb] + sqrt(theta) * z1;
+}
+
+/* Time for a particle at pos moving with vel to reach the internal plate, or
+ * infinity when it does not reach it (moving along or away from the plate's
+ * line, or crossing the line outside the plate's extent). */
+static double plate_time(const uspo_config* g, const double pos[2], const double vel[3])
+{
+    if (!g->plate) return INFINITY;
+    double gap = g->plate_x - pos[0];
+    if (!(gap * vel[0] > 0.0)) return INFINITY;
+    double t = gap / vel[0];
+    double yc = pos[1] + vel[1] * t;
+    if (yc < g->plate_ylo || yc > g->plate_yhi) return INFINITY;
+    return t;
+}
+
+/* Wall-to-wall flight of duration tl in double precision.  Specular faces
+ * mirror the normal velocity, periodic faces wrap, diffuse faces and the
+ * plate re-emit the particle (reemit, wall draws keyed by the hit number)
+ * for the rest of the flight, open faces absorb it.  After 16 hits the
+ * particle is left where it is (counted in *clamped).  Returns 1 when the
+ * particle left through an open face. */
+static int trace(const uspo_config* g, double pos[2], double vel[3], double tl, int src_cell,
+                 int slot, int step, int* clamped)
+{
+    double lo[2] = {g->x0, g->y0}, hi[2] = {g->x1, g->y1};
+    int a_first = g->dim == 2 ? 0 : 1;
+    for (int hit = 0;; ++hit) {
+        if (hit == 16) {
+            for (int a = a_first; a < 2; ++a) {
+                if (pos[a] < lo[a]) pos[a] = lo[a];
+                if (pos[a] > hi[a]) pos[a] = hi[a];
+            }
+            ++*clamped;
+            return 0;
+        }
+        double te = INFINITY;
+        int ax = -1, sd = 0;
+        for (int a = a_first; a < 2; ++a) {
+            double t;
+            int side;
+            if (vel[a] > 0.0) {
+                t = (hi[a] - pos[a]) / vel[a];
+                side = 1;
+            } else if (vel[a] < 0.0) {
+                t = (lo[a] - pos[a]) / vel[a];
+                side = 0;
+            } else {
+                continue;
+            }
+            if (t < te) {
+                te = t;
+                ax = a;
+                sd = side;
+            }
+        }
+        double tp = plate_time(g, pos, vel);
+        int on_plate = tp < te;
+        if (on_plate) te = tp;
+        if (!(te < tl)) {
+            for (int a = a_first; a < 2; ++a) pos[a] += vel[a] * tl;
+            return 0;
+        }
+        if (te < 0.0) te = 0.0;
+        for (int a = a_first; a < 2; ++a) pos[a] += vel[a] * te;
+        tl -= te;
+        uint32_t r[4];
+        if (on_plate) {
+            static const double rest[3] = {0.0, 0.0, 0.0};
+            pos[0] = g->plate_x;
+            draw(g, (uint32_t)step, PUR_WALL, (uint32_t)hit, (uint32_t)src_cell, (uint32_t)slot,
+                 r);
+            /* back to the side it came from */
+            reemit(vel, 0, vel[0] > 0.0, g->kB * g->plate_T / g->m, rest,
+                   uspo_uniform(r[0], g->precision), uspo_uniform(r[1], g->precision),
+                   uspo_uniform(r[2], g->precision));
+            continue;
+        }
+        pos[ax] = sd ? hi[ax] : lo[ax];
+        int face = 2 * ax + sd;
+        int kind = g->face_kind[face];
+        if (kind == 1) {
+            vel[ax] = -vel[ax];
+        } else if (kind == 2) {
+            pos[ax] = sd ? lo[ax] : hi[ax];
+        } else if (kind == 3) {
+            return 1;
+        } else {
+            draw(g, (uint32_t)step, PUR_WALL, (uint32_t)hit, (uint32_t)src_cell, (uint32_t)slot,
+                 r);
+            reemit(vel, ax, sd, g->kB * g->face_T[face] / g->m, g->face_u + 3 * face,
+                   uspo_uniform(r[0], g->precision), uspo_uniform(r[1], g->precision),
+                   uspo_uniform(r[2], g->precision));
+        }
+    }
+}
+
+/* Moves one particle for dt.  A particle that stays inside (and does not
+ * cross the plate's line) moves by one fused multiply-add in the state
+ * precision; any other is traced in double precision (trace).  A body
+ * acceleration (the Poiseuille drive) adds a dt to the velocity afterwards.
+ * Returns the new cell, or -1 when the particle left through an open face. */
 static int advect(const uspo_config* g, part* q, int src_cell, int slot, int step, int* clamped)
 {
     double lo[2] = {g->x0, g->y0}, hi[2] = {g->x1, g->y1};
@@ -555,81 +665,103 @@ static int advect(const uspo_config* g, part* q, int src_cell, int slot, int ste
     int inside = 1;
     for (int a = a_first; a < 2; ++a)
         if (!(np[a] >= lo[a] && np[a] < hi[a])) inside = 0;
+    if (g->plate && ((q->x < g->plate_x) != (np[0] < g->plate_x))) inside = 0;
     if (inside) {
         q->x = np[0];
         q->y = np[1];
     } else {
         double pos[2] = {q->x, q->y}, vel[3] = {q->c[0], q->c[1], q->c[2]};
-        double tl = g->dt;
-        for (int hit = 0;; ++hit) {
-            if (hit == 16) {
-                for (int a = a_first; a < 2; ++a) {
-                    if (pos[a] < lo[a]) pos[a] = lo[a];
-                    if (pos[a] > hi[a]) pos[a] = hi[a];
-                }
-                ++*clamped;
-                break;
-            }
-            double te = INFINITY;
-            int ax = -1, sd = 0;
-            for (int a = a_first; a < 2; ++a) {
-                double t;
-                int side;
-                if (vel[a] > 0.0) {
-                    t = (hi[a] - pos[a]) / vel[a];
-                    side = 1;
-                } else if (vel[a] < 0.0) {
-                    t = (lo[a] - pos[a]) / vel[a];
-                    side = 0;
-                } else {
-                    continue;
-                }
-                if (t < te) {
-                    te = t;
-                    ax = a;
-                    sd = side;
-                }
-            }
-            if (!(te < tl)) {
-                for (int a = a_first; a < 2; ++a) pos[a] += vel[a] * tl;
-                break;
-            }
-            if (te < 0.0) te = 0.0;
-            for (int a = a_first; a < 2; ++a) pos[a] += vel[a] * te;
-            pos[ax] = sd ? hi[ax] : lo[ax];
-            tl -= te;
-            int face = 2 * ax + sd;
-            int kind = g->face_kind[face];
-            if (kind == 1) {
-                vel[ax] = -vel[ax];
-            } else if (kind == 2) {
-                pos[ax] = sd ? lo[ax] : hi[ax];
-            } else {
-                uint32_t r[4];
-                draw(g, (uint32_t)step, PUR_WALL, (uint32_t)hit, (uint32_t)src_cell,
-                     (uint32_t)slot, r);
-                double Tw = g->face_T[face];
-                double thw = g->kB * Tw / g->m;
-                double u0 = uspo_uniform(r[0], g->precision);
-                double u1 = uspo_uniform(r[1], g->precision);
-                double u2 = uspo_uniform(r[2], g->precision);
-                double vn = sqrt(-2.0 * thw * log(u0));
-                double rad = sqrt(-2.0 * log(u1));
-                double z0 = rad * cos(2.0 * M_PI * u2), z1 = rad * sin(2.0 * M_PI * u2);
-                int vi = ax; /* velocity component normal to the face: x for axis 0, y for 1 */
-                int ta = vi == 0 ? 1 : 0, tb = 2;
-                const double* uw = g->face_u + 3 * face;
-                vel[vi] = sd ? -vn : vn;
-                vel[ta] = uw[ta] + sqrt(thw) * z0;
-                vel[tb] = uw[tb] + sqrt(thw) * z1;
-            }
-        }
+        if (trace(g, pos, vel, g->dt, src_cell, slot, step, clamped)) return -1;
         q->x = g->dim == 2 ? st(g, pos[0]) : q->x;
         q->y = st(g, pos[1]);
         for (int k = 0; k < 3; ++k) q->c[k] = st(g, vel[k]);
     }
     for (int k = 0; k < 3; ++k)
         if (g->accel[k] != 0.0) q->c[k] = st(g, q->c[k] + st(g, g->accel[k] * g->dt));
+    return cell_of(g, q->x, q->y);
+}
+
+/* Open faces (kind 3).  Does open face `face` bound cell c?  If so, *area is
+ * the face's area per cell (unit area in 1-D, dx or dy per unit depth in
+ * 2-D) and *n, *theta the state of the reservoir behind it. */
+static int open_face_of(const uspo_config* g, int c, int face, double* area, double* n,
+                        double* theta)
+{
+    if (g->face_kind[face] != 3) return 0;
+    int ax = face / 2, sd = face % 2, ix, iy;
+    if (g->dim == 1 && ax == 0) return 0;
+    cell_ij(g, c, &ix, &iy);
+    if (ax == 1 && iy != (sd ? g->ny - 1 : 0)) return 0;
+    if (ax == 0 && ix != (sd ? g->nx - 1 : 0)) return 0;
+    double tc = 0.0, T = g->face_T[face];
+    *n = g->face_n[face];
+    if (g->dim == 2) {
+        tc = ax == 1 ? g->x0 + ((double)ix + 0.5) * g->dx : g->y0 + ((double)iy + 0.5) * g->dy;
+        if (tc >= g->face_split[face]) {
+            *n = g->face_nb[face];
+            T = g->face_Tb[face];
+        }
+        *area = ax == 1 ? g->dx : g->dy;
+    } else {
+        *area = 1.0;
+    }
+    *theta = g->kB * T / g->m;
+    return 1;
+}
+
+/* Number of particles entering cell c through open face `face` in one step:
+ * the one-sided flux of a gas at rest, n sqrt(theta / (2 pi)) per unit area
+ * and time (the kinetic-theory effusion rate), times area and dt over N_p,
+ * stochastically rounded. */
+static int inject_count(const uspo_config* g, int step, int c, int face)
+{
+    double area, n, theta;
+    if (!open_face_of(g, c, face, &area, &n, &theta)) return 0;
+    double v = n * sqrt(theta / (2.0 * M_PI)) * area * g->dt / g->Np;
+    uint32_t r[4];
+    draw(g, (uint32_t)step, PUR_INJECT_CNT, (uint32_t)face, (uint32_t)c, 0, r);
+    double u = uspo_uniform(r[0], g->precision);
+    double fl = floor(v);
+    return (int)fl + (u < v - fl ? 1 : 0);
+}
+
+/* Entering particle k of cell c through open face `face` (slot = its slot in
+ * the cell, after the particles present): it crosses the face at a uniform
+ * point of the cell's face segment, at a uniform time of the step, with a
+ * velocity from the flux-weighted half-range Maxwellian of the reservoir
+ * (normal speed sqrt(-2 theta ln u), tangential face velocity plus a
+ * Maxwellian), weight 1, and flies for the rest of the step (trace).
+ * Returns the new cell or -1 (it left again through an open face). */
+static int inject_one(const uspo_config* g, int step, int c, int face, int k, int slot, part* q,
+                      int* clamped)
+{
+    double area, n, theta;
+    open_face_of(g, c, face, &area, &n, &theta);
+    int ax = face / 2, sd = face % 2, ix, iy;
+    cell_ij(g, c, &ix, &iy);
+    uint32_t r[4];
+    draw(g, (uint32_t)step, PUR_INJECT, (uint32_t)face, (uint32_t)c, (uint32_t)k, r);
+    double vel[3], pos[2];
+    reemit(vel, ax, sd, theta, g->face_u + 3 * face, uspo_uniform(r[0], g->precision),
+           uspo_uniform(r[1], g->precision), uspo_uniform(r[2], g->precision));
+    double tl = uspo_uniform(r[3], g->precision) * g->dt;
+    pos[0] = 0.0;
+    if (ax == 1) {
+        pos[1] = sd ? g->y1 : g->y0;
+        if (g->dim == 2) {
+            draw(g, (uint32_t)step, PUR_INJECT_POS, (uint32_t)face, (uint32_t)c, (uint32_t)k, r);
+            pos[0] = g->x0 + ((double)ix + uspo_uniform(r[0], g->precision)) * g->dx;
+        }
+    } else {
+        pos[0] = sd ? g->x1 : g->x0;
+        draw(g, (uint32_t)step, PUR_INJECT_POS, (uint32_t)face, (uint32_t)c, (uint32_t)k, r);
+        pos[1] = g->y0 + ((double)iy + uspo_uniform(r[0], g->precision)) * g->dy;
+    }
+    if (trace(g, pos, vel, tl, c, slot, step, clamped)) return -1;
+    q->x = g->dim == 2 ? st(g, pos[0]) : 0.0;
+    q->y = st(g, pos[1]);
+    for (int d = 0; d < 3; ++d) q->c[d] = st(g, vel[d]);
+    q->w = 1.0;
     return cell_of(g, q->x, q->y);
 }
 
@@ -1052,6 +1184,24 @@ static int check_config(const uspo_config* g)
     if (!(g->dt > 0) || !(g->Np > 0) || !(g->vcell > 0) || !(g->r_p > 0)) return -1;
     if (g->precision != 32 && g->precision != 64) return -1;
     if (g->max_ppc < 2 || g->max_ppc > 2048) return -1;
+    int open = 0;
+    for (int f = 0; f < 4; ++f) {
+        if (g->face_kind[f] < 0 || g->face_kind[f] > 3) return -1;
+        if (g->face_kind[f] != 3) continue;
+        open = 1;
+        if (!(g->face_n[f] >= 0.0) || !(g->face_nb[f] >= 0.0)) return -1;
+        if (!(g->face_T[f] > 0.0) || !(g->face_Tb[f] > 0.0)) return -1;
+        if (g->face_u[3 * f + f / 2] != 0.0) return -1;
+    }
+    /* a periodic face needs a periodic partner */
+    if ((g->face_kind[0] == 2) != (g->face_kind[1] == 2)) return -1;
+    if ((g->face_kind[2] == 2) != (g->face_kind[3] == 2)) return -1;
+    /* entering particles fly for part of a step: no body force with them */
+    if (open && (g->accel[0] != 0.0 || g->accel[1] != 0.0 || g->accel[2] != 0.0)) return -1;
+    if (g->plate) {
+        if (g->dim != 2 || !(g->plate_x > g->x0 && g->plate_x < g->x1)) return -1;
+        if (!(g->plate_ylo <= g->plate_yhi) || !(g->plate_T > 0.0)) return -1;
+    }
     return 0;
 }
 
@@ -1167,17 +1317,39 @@ static void one_step(uspo* o)
         if (o->cell[c].n > g->max_ppc) o->error = -3;
     }
 
-    /* step 3: advection + walls, then the stable sort by new cell */
+    /* step 3: advection + walls, the particles entering through open faces
+     * (after those present, faces in index order), then the stable sort by
+     * new cell; particles leaving through open faces are dropped */
     long long total = 0;
-    for (int c = 0; c < nc; ++c) total += o->cell[c].n;
+    int* ninj = (int*)calloc((size_t)nc * 4, sizeof(int));
+    for (int c = 0; c < nc; ++c) {
+        int t = 0;
+        for (int f = 0; f < 4; ++f) t += ninj[4 * c + f] = inject_count(g, o->step, c, f);
+        if (o->cell[c].n + t > g->max_ppc) o->error = -3;
+        o->diag[(size_t)USPO_NDIAG * c + D_NINJ] = t;
+        total += o->cell[c].n + t;
+    }
     sentry* e = (sentry*)malloc(sizeof(sentry) * (size_t)(total + 1));
     long long k = 0;
     int perx = g->face_kind[0] == 2, pery = g->face_kind[2] == 2;
     for (int c = 0; c < nc; ++c) {
-        int clamped = 0;
-        for (int s = 0; s < o->cell[c].n; ++s) {
-            part q = o->cell[c].p[s];
-            int dcell = advect(g, &q, c, s, o->step, &clamped);
+        int clamped = 0, gone = 0, n = o->cell[c].n;
+        for (int s = 0; s < n + ninj[4 * c] + ninj[4 * c + 1] + ninj[4 * c + 2] + ninj[4 * c + 3];
+             ++s) {
+            part q;
+            int dcell;
+            if (s < n) {
+                q = o->cell[c].p[s];
+                dcell = advect(g, &q, c, s, o->step, &clamped);
+            } else {
+                int f = 0, j = s - n;
+                while (j >= ninj[4 * c + f]) j -= ninj[4 * c + f++];
+                dcell = inject_one(g, o->step, c, f, j, s, &q, &clamped);
+            }
+            if (dcell < 0) {
+                ++gone;
+                continue;
+            }
             int sx = c % g->nx, sy = c / g->nx, dx = dcell % g->nx, dy = dcell / g->nx;
             e[k].dest = dcell;
             e[k].dy = min_image(sy - dy, g->ny, pery);
@@ -1187,10 +1359,12 @@ static void one_step(uspo* o)
             ++k;
         }
         o->diag[(size_t)USPO_NDIAG * c + D_CLAMP] = clamped;
+        o->diag[(size_t)USPO_NDIAG * c + D_NGONE] = gone;
         o->cell[c].n = 0;
     }
-    qsort(e, (size_t)total, sizeof(sentry), cmp_entry);
-    for (long long i = 0; i < total; ++i) pl_push(&o->cell[e[i].dest], e[i].q);
+    free(ninj);
+    qsort(e, (size_t)k, sizeof(sentry), cmp_entry);
+    for (long long i = 0; i < k; ++i) pl_push(&o->cell[e[i].dest], e[i].q);
     free(e);
 
     /* steps 4-8 */
@@ -1399,7 +1573,8 @@ int uspo_test_fields(const uspo_config* cfg, const double* parts, int n, double*
     return 0;
 }
 
-/* advects one particle [x, y, cx, cy, cz, w] in place; returns the new cell */
+/* advects one particle [x, y, cx, cy, cz, w] in place; returns the new cell
+ * (-1: it left through an open face) */
 int uspo_test_advect(const uspo_config* cfg, double* r, int src_cell, int slot, int step)
 {
     part q;
@@ -1408,6 +1583,26 @@ int uspo_test_advect(const uspo_config* cfg, double* r, int src_cell, int slot, 
     int d = advect(cfg, &q, src_cell, slot, step, &clamped);
     r[0] = q.x; r[1] = q.y; r[2] = q.c[0]; r[3] = q.c[1]; r[4] = q.c[2]; r[5] = q.w;
     return d;
+}
+
+/* The particles entering cell c through face `face` at step `step`: up to
+ * max_out records (x, y, cx, cy, cz, w, destination cell) into out, the
+ * first one at slot `slot0`; a particle that left again has cell -1.
+ * Returns the count (-1 for a bad configuration). */
+int uspo_test_inject(const uspo_config* cfg, int step, int cell, int face, int slot0,
+                     double* out, int max_out)
+{
+    if (check_config(cfg)) return -1;
+    int n = inject_count(cfg, step, cell, face);
+    for (int k = 0; k < n && k < max_out; ++k) {
+        part q = {0};
+        int clamped = 0;
+        int d = inject_one(cfg, step, cell, face, k, slot0 + k, &q, &clamped);
+        double* r = out + 7 * (size_t)k;
+        r[0] = q.x; r[1] = q.y; r[2] = q.c[0]; r[3] = q.c[1]; r[4] = q.c[2]; r[5] = q.w;
+        r[6] = d;
+    }
+    return n;
 }
 
 /* P_ne of every cell from given centred moments (validity needs S0 > 0 and a

@@ -28,7 +28,8 @@ typedef struct {
     /* uniform Cartesian grid; 1-D resolves y only, 2-D resolves x and y */
     int dim, nx, ny;
     double x0, x1, y0, y1, dx, dy, inv_dx, inv_dy, vcell;
-    /* faces 0..3 = x-lo, x-hi, y-lo, y-hi; kind 0 diffuse, 1 specular, 2 periodic */
+    /* faces 0..3 = x-lo, x-hi, y-lo, y-hi; kind 0 diffuse, 1 specular,
+     * 2 periodic, 3 open (a reservoir: see face_n below) */
     int face_kind[4];
     double face_T[4];
     double face_u[12];
@@ -46,6 +47,18 @@ typedef struct {
      * then the fixed window n_avg from the first sample (both averages: the
      * Eq. 34 fields and the averages of f-tilde^*) */
     int avg_init;
+    /* open faces (kind 3): the domain touches a reservoir of gas with number
+     * density face_n, temperature face_T and velocity face_u (its component
+     * normal to the face must be 0).  Where the face's tangential coordinate
+     * (x on a y face, y on an x face; 2-D only) is >= face_split, the
+     * reservoir has density face_nb and temperature face_Tb instead (a face
+     * bordering two chambers). */
+    double face_n[4], face_split[4], face_nb[4], face_Tb[4];
+    /* internal plate (2-D only): a thin diffuse wall at rest at temperature
+     * plate_T on the line x = plate_x, x0 < plate_x < x1, covering
+     * plate_ylo <= y <= plate_yhi; both sides reflect */
+    int plate;
+    double plate_x, plate_ylo, plate_yhi, plate_T;
 } uspo_config;
 
 /* per-cell state record: centred moments, raw sums, averaged raw sums of f^n,
@@ -84,6 +97,8 @@ int uspo_test_spawn(const uspo_config* cfg, const double mom[USPO_MOM], int n_pa
 int uspo_test_fields(const uspo_config* cfg, const double* parts, int n, double* out_mom,
                      double* out_fields);
 int uspo_test_advect(const uspo_config* cfg, double* part6, int src_cell, int slot, int step);
+int uspo_test_inject(const uspo_config* cfg, int step, int cell, int face, int slot0,
+                     double* out, int max_out);
 int uspo_test_pne(const uspo_config* cfg, const double* mom, double* pne_out);
 
 #ifdef __cplusplus

@@ -17,7 +17,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
 
 
 SOURCES = ("usp_cell_f32_1d.hip", "usp_cell_f32_2d.hip", "usp_cell_f64_1d.hip",
-           "usp_cell_f64_2d.hip", "usp_kernels.hip", "usp_runtime.hip")
+           "usp_cell_f64_2d.hip", "usp_cell_f32_1d_xb.hip", "usp_cell_f32_2d_xb.hip",
+           "usp_cell_f64_1d_xb.hip", "usp_cell_f64_2d_xb.hip", "usp_kernels.hip",
+           "usp_runtime.hip")
 
 
 def build(verbose: bool = False) -> str:

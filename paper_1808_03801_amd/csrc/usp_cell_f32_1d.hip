@@ -2,5 +2,5 @@
 #include "usp_cell_impl.h"
 
 namespace usp {
-USP_CELL_ALL(float, 1)
+USP_CELL_ALL(float, 1, false)
 }  // namespace usp

@@ -2,5 +2,5 @@
 #include "usp_cell_impl.h"
 
 namespace usp {
-USP_CELL_ALL(double, 2)
+USP_CELL_ALL(double, 2, false)
 }  // namespace usp

@@ -616,7 +616,7 @@ struct GatherState {
 // caller reruns it with a larger shape (the gather state is reused), else
 // the cell is appended to tier_out for the next launch.  carve_cap is the
 // slot count the LDS tables are laid out for (the largest shape of the launch).
-template <int NT, typename real, int DIM, int PPT>
+template <int NT, typename real, int DIM, int PPT, bool XB>
 __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                                               unsigned char* smem, int tid, int g, int* tier_out,
                                               int tier_len, int carve_cap, bool retry_local,
@@ -822,7 +822,9 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     if (mode & MODE_RELAX) {
         if (dg && tid == 0) {
             for (int k = 0; k < NDIAG_STEP; ++k)
-                if (k != D_N2 && k != D_CLAMP && k != D_MARG_CNT2) dg[k] = 0.0;
+                if (k != D_N2 && k != D_CLAMP && k != D_MARG_CNT2 && k != D_NINJ &&
+                    k != D_NGONE)
+                    dg[k] = 0.0;
             dg[D_NIN] = n0;
         }
         {
@@ -1118,7 +1120,16 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
         // step 3 for particles at physical positions [lo, hi): advect, walls,
         // destination bin; a particle leaving the sort window is marked and
         // goes to the far list only once the cell can no longer be handed on
-        int clamps = 0;
+        int clamps = 0, gone = 0;
+        // sort-window bin of destination cell d (FAR_PENDING: beyond the window)
+        auto bin_key = [&](int d) -> uint32_t {
+            const int dy_ = DIM == 2 ? d / I.nx : d;
+            const int dx_ = DIM == 2 ? d - dy_ * I.nx : 0;
+            const int oy = min_image(iy - dy_, I.ny, per_y);
+            const int ox = DIM == 2 ? min_image(ix - dx_, I.nx, per_x) : 0;
+            if (oy < -I.Ky || oy > I.Ky || ox < -I.Kx || ox > I.Kx) return FAR_PENDING;
+            return (uint32_t)((oy + I.Ky) * I.nbx + (ox + I.Kx));
+        };
         auto move = [&](int lo, int hi, bool reset) {
             const int hiu = uni(hi);
 #pragma unroll
@@ -1130,20 +1141,19 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                     real v0 = P.c0[k], v1 = P.c1[k], v2 = P.c2[k];
                     const int slot = (int)(P.st[k] >> 8);
                     const int d =
-                        advect<real, DIM>(I, px, py, v0, v1, v2, c, slot, mstep, &clamps);
+                        advect<real, DIM, XB>(I, px, py, v0, v1, v2, c, slot, mstep, &clamps);
                     if (DIM == 2) P.x[k] = px;
                     P.y[k] = py;
                     P.c0[k] = v0;
                     P.c1[k] = v1;
                     P.c2[k] = v2;
-                    const int dy_ = DIM == 2 ? d / I.nx : d;
-                    const int dx_ = DIM == 2 ? d - dy_ * I.nx : 0;
-                    const int oy = min_image(iy - dy_, I.ny, per_y);
-                    const int ox = DIM == 2 ? min_image(ix - dx_, I.nx, per_x) : 0;
-                    if (oy < -I.Ky || oy > I.Ky || ox < -I.Kx || ox > I.Kx)
-                        P.key[k] = FAR_PENDING;
-                    else
-                        P.key[k] = (uint32_t)((oy + I.Ky) * I.nbx + (ox + I.Kx));
+                    // a particle gone through an open face is not written
+                    if (XB && d < 0) {
+                        P.key[k] = FAR_BIN;
+                        ++gone;
+                    } else {
+                        P.key[k] = bin_key(d);
+                    }
                 } else if (reset) {
                     P.key[k] = FAR_BIN;
                 }
@@ -1158,11 +1168,70 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
         const int n2 = spawn_r<NT>(I, P, L, 2, c, ix, iy, mstep, f, P2, nphys, nlog, tid, &errbits,
                                &mc2, can_defer);
         if (n2 < 0) return defer(2);
+        // particles entering through open faces: counted before the last
+        // capacity decision, created after the step-2 particles (slots in
+        // face order)
+        int ninj[4] = {0, 0, 0, 0};
+        int nin = 0;
+        if (XB && I.open_mask) {
+#pragma unroll
+            for (int fc = 0; fc < 4; ++fc) {
+                ninj[fc] = inject_count<DIM>(I, c, ix, iy, fc, mstep);
+                nin += ninj[fc];
+            }
+            const int need_log = nlog + n2 + nin, need_phys = nphys + n2 + nin;
+            if (need_log > I.max_ppc || need_phys > CAP) {
+                if (can_defer && need_log <= I.max_ppc) return defer(2);
+                errbits |= ERR_CAPACITY;
+                int room = I.max_ppc - nlog - n2 < CAP - nphys - n2 ? I.max_ppc - nlog - n2
+                                                                    : CAP - nphys - n2;
+                room = room < 0 ? 0 : room;
+                nin = 0;
+#pragma unroll
+                for (int fc = 0; fc < 4; ++fc) {
+                    ninj[fc] = ninj[fc] < room - nin ? ninj[fc] : room - nin;
+                    nin += ninj[fc];
+                }
+            }
+        }
         commit();
         nphys += n2;
         nlog += n2;
         mark(10);
         if (n2 > 0) move(nphys0, nphys, false);
+        if (XB && nin > 0) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int j = k * NT + tid;
+                if (k * NT + NT > nphys && k * NT < nphys + nin && j >= nphys &&
+                    j < nphys + nin) {
+                    const int q = j - nphys;
+                    int fq = 0, qf = q, acc = 0;
+#pragma unroll
+                    for (int fc = 0; fc < 4; ++fc) {
+                        if (q >= acc && q < acc + ninj[fc]) {
+                            fq = fc;
+                            qf = q - acc;
+                        }
+                        acc += ninj[fc];
+                    }
+                    real px = (real)0, py = (real)0, v0 = (real)0, v1 = (real)0, v2 = (real)0;
+                    const int d = inject_one<real, DIM>(I, c, ix, iy, fq, qf, nlog + q, mstep, px,
+                                                        py, v0, v1, v2, &clamps);
+                    if (DIM == 2) P.x[k] = px;
+                    P.y[k] = py;
+                    P.c0[k] = v0;
+                    P.c1[k] = v1;
+                    P.c2[k] = v2;
+                    P.w[k] = (real)1;
+                    P.st[k] = (uint32_t)FT_KEEP | ((uint32_t)(nlog + q) << 8);
+                    P.key[k] = d < 0 ? (uint32_t)FAR_BIN : bin_key(d);
+                    gone += d < 0;
+                }
+            }
+            nphys += nin;
+            nlog += nin;
+        }
         // far movers: appended now, with their destination cell and offsets
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -1261,12 +1330,14 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
         for (int b = tid; b <= nb; b += NT) tout[b] = L.boff[b];
         mark(13);
         if (dg) {
-            double cl[1] = {(double)clamps};
+            double cl[2] = {(double)clamps, (double)gone};
             bsum<NT>(cl, L.red, tid);
             if (tid == 0) {
                 dg[D_N2] = n2;
                 dg[D_CLAMP] = cl[0];
                 dg[D_MARG_CNT2] = mc2;
+                dg[D_NINJ] = nin;
+                dg[D_NGONE] = cl[1];
             }
         }
     } else {
@@ -1309,7 +1380,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     return 0;
 }
 
-template <typename real, int DIM, int NT, int PPT, int PPT2>
+template <typename real, int DIM, int NT, int PPT, int PPT2, bool XB>
 __global__ void __launch_bounds__(NT) cell_kernel(Batch B)
 {
     // one workgroup per cell (no loop over cells: a loop would let the
@@ -1334,24 +1405,26 @@ __global__ void __launch_bounds__(NT) cell_kernel(Batch B)
     const InstDev& I = B.inst[lo];
     const int c = g - B.base[lo];
     if constexpr (PPT2 == 0) {
-        process_cell_r<NT, real, DIM, PPT>(I, c, B.mode, smem, tid, g, B.tier_out, B.ncells,
+        process_cell_r<NT, real, DIM, PPT, XB>(I, c, B.mode, smem, tid, g, B.tier_out, B.ncells,
                                            NT * PPT, false, gs);
     } else {
         // PPT slots per thread first; cells that need more rerun with PPT2
-        if (process_cell_r<NT, real, DIM, PPT>(I, c, B.mode, smem, tid, g, nullptr, 0, NT * PPT2,
+        if (process_cell_r<NT, real, DIM, PPT, XB>(I, c, B.mode, smem, tid, g, nullptr, 0, NT * PPT2,
                                                true, gs) != 0)
-            process_cell_r<NT, real, DIM, PPT2>(I, c, B.mode, smem, tid, g, B.tier_out, B.ncells,
+            process_cell_r<NT, real, DIM, PPT2, XB>(I, c, B.mode, smem, tid, g, B.tier_out, B.ncells,
                                                 NT * PPT2, false, gs);
     }
 }
 
-#define USP_CELL_INST(R, D, NT, PPT, PPT2) \
-    template __global__ void cell_kernel<R, D, NT, PPT, PPT2>(Batch);
-#define USP_CELL_ALL(R, D)            \
-    USP_CELL_INST(R, D, 256, 1, 0)    \
-    USP_CELL_INST(R, D, 256, 2, 0)    \
-    USP_CELL_INST(R, D, 256, 4, 0)    \
-    USP_CELL_INST(R, D, 256, 4, 6)    \
-    USP_CELL_INST(R, D, 256, 8, 0)
+// XB: the extended boundary set (open faces, the internal plate); instances
+// without them run the variant that leaves that code out
+#define USP_CELL_INST(R, D, NT, PPT, PPT2, XB) \
+    template __global__ void cell_kernel<R, D, NT, PPT, PPT2, XB>(Batch);
+#define USP_CELL_ALL(R, D, XB)            \
+    USP_CELL_INST(R, D, 256, 1, 0, XB)    \
+    USP_CELL_INST(R, D, 256, 2, 0, XB)    \
+    USP_CELL_INST(R, D, 256, 4, 0, XB)    \
+    USP_CELL_INST(R, D, 256, 4, 6, XB)    \
+    USP_CELL_INST(R, D, 256, 8, 0, XB)
 
 }  // namespace usp

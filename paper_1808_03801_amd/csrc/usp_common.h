@@ -36,14 +36,17 @@ enum {
     PUR_SPAWN_VEL = 5,
     PUR_WALL = 6,
     PUR_SELECT = 7,
-    PUR_RESAMPLE = 8
+    PUR_RESAMPLE = 8,
+    PUR_INJECT_CNT = 9,
+    PUR_INJECT = 10,
+    PUR_INJECT_POS = 11
 };
 
 // diagnostic slots (same meaning as the host-side record)
 enum {
     D_NIN = 0, D_N4, D_NSEL, D_NUSP, D_NDEL, D_N7, D_NOUT, D_N2, D_SSEL, D_PSEL, D_FLAGS,
     D_CHOLFB, D_M0, D_P0X, D_P0Y, D_P0Z, D_E0, D_M1, D_P1X, D_P1Y, D_P1Z, D_E1, D_CLAMP,
-    D_MARG_SEL, D_MARG_ROUND, D_MARG_CNT, D_WR, D_S2, D_MARG_CNT2
+    D_MARG_SEL, D_MARG_ROUND, D_MARG_CNT, D_WR, D_S2, D_MARG_CNT2, D_NINJ, D_NGONE
 };
 enum { F_SKIP = 1, F_FAILMASS = 2, F_FAILENERGY = 4, F_NOUSP = 8 };
 // device-only diagnostic slot: particle slots of the shape that finished the cell
@@ -61,6 +64,13 @@ struct InstDev {
     double face_T[4];
     double face_u[12];
     double accel[3];
+    // open faces (kind 3): reservoir density, and the second chamber's state
+    // beyond the split coordinate; bit f of open_mask set for an open face f
+    double face_n[4], face_split[4], face_nb[4], face_Tb[4];
+    int open_mask;
+    // internal plate (2-D): thin diffuse wall on x = plate_x, plate_ylo <= y <= plate_yhi
+    int plate;
+    double plate_x, plate_ylo, plate_yhi, plate_T;
     // numerics
     double dt, r_p, Kn_c, pne_fixed;
     int pne_mode, n_avg, avg_start, prec, weight_mode, conserve_mode, max_ppc, jmom_mode, proj;

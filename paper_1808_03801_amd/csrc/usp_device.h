@@ -299,107 +299,139 @@ __device__ __forceinline__ void psi5(double c0, double c1, double c2, const doub
 
 // ---------------------------------------------------------------------------
 // Step 3 for one particle: free flight by one fused multiply-add in the state
-// precision; particles leaving the domain are traced wall to wall in double.
-// Returns the destination cell.
+// precision; particles leaving the domain or crossing the plate's line are
+// traced wall to wall in double.  Returns the destination cell (-1: the
+// particle left through an open face).
 // ---------------------------------------------------------------------------
-// Wall-to-wall trace of a particle that leaves the domain during the step
-// (double precision).  Inlined: an out-of-line call makes the caller keep its
-// particle registers clear of the call-clobbered ones, which costs more
-// registers than the inlined trace itself.
 template <typename real>
 struct Flight {
     real px, py, c0, c1, c2;
     int clamped;
+    bool gone;
 };
 
-// Values in, values out: no address of the caller's registers escapes.
-template <typename real, int DIM>
+// Full-accommodation re-emission off a surface normal to `axis`; sd = 1 when
+// the surface faces the -axis direction.  Normal speed sqrt(-2 theta ln u0),
+// tangential uw plus a Maxwellian from the Box-Muller pair (u1, u2).
+__device__ __forceinline__ void reemit(double vel[3], int axis, int sd, double theta,
+                                       const double* uw, double u0, double u1, double u2)
+{
+    const double vn = sqrt(-2.0 * theta * log(u0));
+    const double rad = sqrt(-2.0 * log(u1));
+    double s, c;
+    sincospi(2.0 * u2, &s, &c);
+    const int ta = axis == 0 ? 1 : 0, tb = 2;
+    const double sth = sqrt(theta);
+    vel[axis] = sd ? -vn : vn;
+    vel[ta] = uw[ta] + sth * (rad * c);
+    vel[tb] = uw[tb] + sth * (rad * s);
+}
+
+// Wall-to-wall trace of a flight of duration tl in double precision, in
+// place on pos / vel.  Specular faces mirror, periodic faces wrap, diffuse
+// faces and the plate re-emit (wall draws keyed by the hit number), open
+// faces absorb: returns true when the particle left through one.  After 16
+// hits the particle is left where it is (counted in clamped).  Inlined: an
+// out-of-line call makes the caller keep its particle registers clear of the
+// call-clobbered ones, which costs more registers than the trace itself.
+template <int DIM, bool XB>
+__device__ __forceinline__ bool trace_d(const InstDev& I, double* pos, double* vel, double tl,
+                                        int src_cell, int slot, uint32_t step, int& clamped)
+{
+    const double lo[2] = {I.x0, I.y0}, hi[2] = {I.x1, I.y1};
+    const double rest[3] = {0.0, 0.0, 0.0};
+    const int a0 = DIM == 2 ? 0 : 1;
+    for (int hit = 0;; ++hit) {
+        if (hit == 16) {
+            for (int a = a0; a < 2; ++a) {
+                if (pos[a] < lo[a]) pos[a] = lo[a];
+                if (pos[a] > hi[a]) pos[a] = hi[a];
+            }
+            ++clamped;
+            return false;
+        }
+        double te = __builtin_inf();
+        int ax = -1, sd = 0;
+        for (int a = a0; a < 2; ++a) {
+            double t;
+            int side;
+            if (vel[a] > 0.0) {
+                t = (hi[a] - pos[a]) / vel[a];
+                side = 1;
+            } else if (vel[a] < 0.0) {
+                t = (lo[a] - pos[a]) / vel[a];
+                side = 0;
+            } else {
+                continue;
+            }
+            if (t < te) {
+                te = t;
+                ax = a;
+                sd = side;
+            }
+        }
+        bool on_plate = false;
+        if (XB && DIM == 2 && I.plate) {
+            // the plate's line, reached while moving towards it, inside its extent
+            const double gap = I.plate_x - pos[0];
+            if (gap * vel[0] > 0.0) {
+                const double t = gap / vel[0];
+                const double yc = pos[1] + vel[1] * t;
+                if (!(yc < I.plate_ylo || yc > I.plate_yhi) && t < te) {
+                    te = t;
+                    on_plate = true;
+                }
+            }
+        }
+        if (!(te < tl)) {
+            for (int a = a0; a < 2; ++a) pos[a] += vel[a] * tl;
+            return false;
+        }
+        if (te < 0.0) te = 0.0;
+        for (int a = a0; a < 2; ++a) pos[a] += vel[a] * te;
+        tl -= te;
+        uint32_t r[4];
+        if (on_plate) {
+            pos[0] = I.plate_x;
+            draw(I, step, PUR_WALL, (uint32_t)hit, (uint32_t)src_cell, (uint32_t)slot, r);
+            // back to the side it came from
+            reemit(vel, 0, vel[0] > 0.0 ? 1 : 0, I.kB * I.plate_T / I.m, rest,
+                   uni_d(r[0], I.prec), uni_d(r[1], I.prec), uni_d(r[2], I.prec));
+            continue;
+        }
+        pos[ax] = sd ? hi[ax] : lo[ax];
+        const int face = 2 * ax + sd;
+        const int kind = I.face_kind[face];
+        if (kind == 1) {
+            vel[ax] = -vel[ax];
+        } else if (kind == 2) {
+            pos[ax] = sd ? lo[ax] : hi[ax];
+        } else if (XB && kind == 3) {
+            return true;
+        } else {
+            draw(I, step, PUR_WALL, (uint32_t)hit, (uint32_t)src_cell, (uint32_t)slot, r);
+            reemit(vel, ax, sd, I.kB * I.face_T[face] / I.m, I.face_u + 3 * face,
+                   uni_d(r[0], I.prec), uni_d(r[1], I.prec), uni_d(r[2], I.prec));
+        }
+    }
+}
+
+// trace_d of a particle held in the state precision for the whole step
+template <typename real, int DIM, bool XB>
 __device__ __forceinline__ Flight<real> wall_trace(const InstDev& I, real px, real py, real c0,
                                                 real c1, real c2, int src_cell, int slot,
                                                 uint32_t step)
 {
-    const double lo[2] = {I.x0, I.y0}, hi[2] = {I.x1, I.y1};
-    int clamped = 0;
-    {
-        double pos[2] = {(double)px, (double)py};
-        double vel[3] = {(double)c0, (double)c1, (double)c2};
-        double tl = I.dt;
-        const int a0 = DIM == 2 ? 0 : 1;
-        for (int hit = 0;; ++hit) {
-            if (hit == 16) {
-                for (int a = a0; a < 2; ++a) {
-                    if (pos[a] < lo[a]) pos[a] = lo[a];
-                    if (pos[a] > hi[a]) pos[a] = hi[a];
-                }
-                ++clamped;
-                break;
-            }
-            double te = __builtin_inf();
-            int ax = -1, sd = 0;
-            for (int a = a0; a < 2; ++a) {
-                double t;
-                int side;
-                if (vel[a] > 0.0) {
-                    t = (hi[a] - pos[a]) / vel[a];
-                    side = 1;
-                } else if (vel[a] < 0.0) {
-                    t = (lo[a] - pos[a]) / vel[a];
-                    side = 0;
-                } else {
-                    continue;
-                }
-                if (t < te) {
-                    te = t;
-                    ax = a;
-                    sd = side;
-                }
-            }
-            if (!(te < tl)) {
-                for (int a = a0; a < 2; ++a) pos[a] += vel[a] * tl;
-                break;
-            }
-            if (te < 0.0) te = 0.0;
-            for (int a = a0; a < 2; ++a) pos[a] += vel[a] * te;
-            pos[ax] = sd ? hi[ax] : lo[ax];
-            tl -= te;
-            const int face = 2 * ax + sd;
-            const int kind = I.face_kind[face];
-            if (kind == 1) {
-                vel[ax] = -vel[ax];
-            } else if (kind == 2) {
-                pos[ax] = sd ? lo[ax] : hi[ax];
-            } else {
-                uint32_t r[4];
-                draw(I, step, PUR_WALL, (uint32_t)hit, (uint32_t)src_cell, (uint32_t)slot, r);
-                const double thw = I.kB * I.face_T[face] / I.m;
-                const double u0 = uni_d(r[0], I.prec), u1 = uni_d(r[1], I.prec);
-                const double u2 = uni_d(r[2], I.prec);
-                const double vn = sqrt(-2.0 * thw * log(u0));
-                const double rad = sqrt(-2.0 * log(u1));
-                double s, c;
-                sincospi(2.0 * u2, &s, &c);
-                const int vi = ax;
-                const int ta = vi == 0 ? 1 : 0, tb = 2;
-                const double* uw = I.face_u + 3 * face;
-                const double sth = sqrt(thw);
-                vel[vi] = sd ? -vn : vn;
-                vel[ta] = uw[ta] + sth * (rad * c);
-                vel[tb] = uw[tb] + sth * (rad * s);
-            }
-        }
-        if (DIM == 2) px = (real)pos[0];
-        py = (real)pos[1];
-        c0 = (real)vel[0];
-        c1 = (real)vel[1];
-        c2 = (real)vel[2];
-    }
     Flight<real> fo;
-    fo.px = px;
-    fo.py = py;
-    fo.c0 = c0;
-    fo.c1 = c1;
-    fo.c2 = c2;
-    fo.clamped = clamped;
+    fo.clamped = 0;
+    double pos[2] = {(double)px, (double)py};
+    double vel[3] = {(double)c0, (double)c1, (double)c2};
+    fo.gone = trace_d<DIM, XB>(I, pos, vel, I.dt, src_cell, slot, step, fo.clamped);
+    fo.px = DIM == 2 ? (real)pos[0] : px;
+    fo.py = (real)pos[1];
+    fo.c0 = (real)vel[0];
+    fo.c1 = (real)vel[1];
+    fo.c2 = (real)vel[2];
     return fo;
 }
 
@@ -417,7 +449,7 @@ __device__ __forceinline__ int cell_index(const InstDev& I, real px, real py)
     return iy * I.nx + ix;
 }
 
-template <typename real, int DIM>
+template <typename real, int DIM, bool XB>
 __device__ __forceinline__ int advect(const InstDev& I, real& px, real& py, real& c0, real& c1,
                                       real& c2, int src_cell, int slot, uint32_t step, int* clamp)
 {
@@ -427,11 +459,18 @@ __device__ __forceinline__ int advect(const InstDev& I, real& px, real& py, real
     np1 = fma(c1, dtr, py);
     bool inside = ((double)np1 >= I.y0) && ((double)np1 < I.y1);
     if (DIM == 2) inside = inside && ((double)np0 >= I.x0) && ((double)np0 < I.x1);
+    if (XB && DIM == 2 && I.plate)
+        inside = inside && (((double)px < I.plate_x) == ((double)np0 < I.plate_x));
     if (inside) {
         px = np0;
         py = np1;
     } else {
-        const Flight<real> fl = wall_trace<real, DIM>(I, px, py, c0, c1, c2, src_cell, slot, step);
+        const Flight<real> fl =
+            wall_trace<real, DIM, XB>(I, px, py, c0, c1, c2, src_cell, slot, step);
+        if (XB && fl.gone) {
+            *clamp += fl.clamped;
+            return -1;
+        }
         px = fl.px;
         py = fl.py;
         c0 = fl.c0;
@@ -445,5 +484,96 @@ __device__ __forceinline__ int advect(const InstDev& I, real& px, real& py, real
     return cell_index<real, DIM>(I, px, py);
 }
 
+
+// Open faces (kind 3).  True when open face `face` bounds cell (ix, iy); then
+// the face's area per cell (unit area in 1-D, dx or dy per unit depth in
+// 2-D) and the density and theta = kT/m of the reservoir behind it (the
+// second state beyond the face's split coordinate, judged at the cell centre).
+template <int DIM>
+__device__ __forceinline__ bool open_face(const InstDev& I, int ix, int iy, int face,
+                                          double& area, double& n, double& theta)
+{
+    if (!((I.open_mask >> face) & 1)) return false;
+    const int ax = face >> 1, sd = face & 1;
+    if (DIM == 1 && ax == 0) return false;
+    if (ax == 1 && iy != (sd ? I.ny - 1 : 0)) return false;
+    if (ax == 0 && ix != (sd ? I.nx - 1 : 0)) return false;
+    double T = I.face_T[face];
+    n = I.face_n[face];
+    if (DIM == 2) {
+        const double tc = ax == 1 ? I.x0 + ((double)ix + 0.5) * I.dx
+                                  : I.y0 + ((double)iy + 0.5) * I.dy;
+        if (tc >= I.face_split[face]) {
+            n = I.face_nb[face];
+            T = I.face_Tb[face];
+        }
+        area = ax == 1 ? I.dx : I.dy;
+    } else {
+        area = 1.0;
+    }
+    theta = I.kB * T / I.m;
+    return true;
+}
+
+// Particles entering cell c through open face `face` in one step: the
+// effusion flux n sqrt(theta / (2 pi)) of the reservoir times area and dt
+// over N_p, stochastically rounded.
+template <int DIM>
+__device__ __forceinline__ int inject_count(const InstDev& I, int c, int ix, int iy, int face,
+                                            uint32_t step)
+{
+    double area, n, theta;
+    if (!open_face<DIM>(I, ix, iy, face, area, n, theta)) return 0;
+    const double v = n * sqrt(theta / (2.0 * M_PI)) * area * I.dt / I.Np;
+    uint32_t r[4];
+    draw(I, step, PUR_INJECT_CNT, (uint32_t)face, (uint32_t)c, 0u, r);
+    const double u = uni_d(r[0], I.prec);
+    const double fl = floor(v);
+    return (int)fl + (u < v - fl ? 1 : 0);
+}
+
+// Entering particle k of cell c through open face `face` (slot: its slot in
+// the cell, after the particles present): it crosses the face at a uniform
+// point of the cell's share of the face and a uniform time of the step, with
+// a velocity from the reservoir's flux-weighted half-range Maxwellian, and
+// flies for the rest of the step (trace_d).  Returns the new cell, or -1
+// when it left again through an open face.
+template <typename real, int DIM>
+__device__ __forceinline__ int inject_one(const InstDev& I, int c, int ix, int iy, int face,
+                                          int k, int slot, uint32_t step, real& px, real& py,
+                                          real& c0, real& c1, real& c2, int* clamp)
+{
+    double area, n, theta;
+    open_face<DIM>(I, ix, iy, face, area, n, theta);
+    const int ax = face >> 1, sd = face & 1;
+    uint32_t r[4];
+    draw(I, step, PUR_INJECT, (uint32_t)face, (uint32_t)c, (uint32_t)k, r);
+    double vel[3], pos[2];
+    reemit(vel, ax, sd, theta, I.face_u + 3 * face, uni_d(r[0], I.prec), uni_d(r[1], I.prec),
+           uni_d(r[2], I.prec));
+    const double tl = uni_d(r[3], I.prec) * I.dt;
+    pos[0] = 0.0;
+    if (ax == 1) {
+        pos[1] = sd ? I.y1 : I.y0;
+        if (DIM == 2) {
+            draw(I, step, PUR_INJECT_POS, (uint32_t)face, (uint32_t)c, (uint32_t)k, r);
+            pos[0] = I.x0 + ((double)ix + uni_d(r[0], I.prec)) * I.dx;
+        }
+    } else {
+        pos[0] = sd ? I.x1 : I.x0;
+        draw(I, step, PUR_INJECT_POS, (uint32_t)face, (uint32_t)c, (uint32_t)k, r);
+        pos[1] = I.y0 + ((double)iy + uni_d(r[0], I.prec)) * I.dy;
+    }
+    int cl = 0;
+    const bool gone = trace_d<DIM, true>(I, pos, vel, tl, c, slot, step, cl);
+    *clamp += cl;
+    if (gone) return -1;
+    px = DIM == 2 ? (real)pos[0] : (real)0;
+    py = (real)pos[1];
+    c0 = (real)vel[0];
+    c1 = (real)vel[1];
+    c2 = (real)vel[2];
+    return cell_index<real, DIM>(I, px, py);
+}
 
 }  // namespace usp

@@ -21,7 +21,7 @@
 #include "usp_common.h"
 
 namespace usp {
-template <typename real, int DIM, int NT, int PPT, int PPT2>
+template <typename real, int DIM, int NT, int PPT, int PPT2, bool XB>
 __global__ void cell_kernel(Batch B);
 template <typename real, int DIM>
 __global__ void init_kernel(Batch B, const double* init_n, const double* init_u,
@@ -47,6 +47,8 @@ struct Instance {
     bool diag_on = false;
     int first = -1;       // first launch shape (-1: the default)
     int top() const { return pick_shape_index(h.max_ppc); }
+    // open faces or the plate: the kernel variant with the extended boundary set
+    int xb() const { return (h.open_mask != 0 || h.plate) ? 1 : 0; }
     int first_shape() const { return first >= 0 ? first : std::min(top(), TIER_FIRST); }
 };
 
@@ -186,6 +188,29 @@ usp_status validate(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb, con
         return fail(ctx, USP_EINVAL, "max_ppc must be in [2, 2048]");
     if (nm->n_avg < 1) return fail(ctx, USP_EINVAL, "n_avg must be >= 1");
     if ((long long)pb->nx * pb->ny > (1LL << 26)) return fail(ctx, USP_EINVAL, "too many cells");
+    bool open = false;
+    for (int f = 0; f < 4; ++f) {
+        const usp_face& fc = pb->face[f];
+        if (fc.kind < USP_BC_DIFFUSE || fc.kind > USP_BC_OPEN)
+            return fail(ctx, USP_EINVAL, "unknown face kind");
+        if (fc.kind != USP_BC_OPEN) continue;
+        open = true;
+        if (!(fc.n >= 0.0) || !(fc.n_b >= 0.0) || !(fc.T > 0.0) || !(fc.T_b > 0.0))
+            return fail(ctx, USP_EINVAL, "open face needs n, n_b >= 0 and T, T_b > 0");
+        if (fc.u[f / 2] != 0.0)
+            return fail(ctx, USP_EINVAL, "open face reservoir moves across the face");
+    }
+    if ((pb->face[0].kind == USP_BC_PERIODIC) != (pb->face[1].kind == USP_BC_PERIODIC) ||
+        (pb->face[2].kind == USP_BC_PERIODIC) != (pb->face[3].kind == USP_BC_PERIODIC))
+        return fail(ctx, USP_EINVAL, "a periodic face needs a periodic opposite face");
+    if (open && (pb->accel[0] != 0.0 || pb->accel[1] != 0.0 || pb->accel[2] != 0.0))
+        return fail(ctx, USP_EINVAL, "open faces cannot be combined with a body acceleration");
+    if (pb->plate) {
+        if (pb->dim != 2 || !(pb->plate_x > pb->x0 && pb->plate_x < pb->x1))
+            return fail(ctx, USP_EINVAL, "plate needs 2-D and x0 < plate_x < x1");
+        if (!(pb->plate_ylo <= pb->plate_yhi) || !(pb->plate_T > 0.0))
+            return fail(ctx, USP_EINVAL, "plate needs plate_ylo <= plate_yhi and plate_T > 0");
+    }
     return USP_OK;
 }
 
@@ -220,15 +245,15 @@ usp_status with_kernel(int prec, int dim, F f)
     return f((double*)nullptr, std::integral_constant<int, 2>());
 }
 
-template <typename real, int D>
+template <typename real, int D, bool XB>
 const void* cell_kernel_for(Shape sh)
 {
-    if (sh.ppt2 == 6) return (const void*)cell_kernel<real, D, 256, 4, 6>;
+    if (sh.ppt2 == 6) return (const void*)cell_kernel<real, D, 256, 4, 6, XB>;
     switch (sh.ppt) {
-        case 1: return (const void*)cell_kernel<real, D, 256, 1, 0>;
-        case 2: return (const void*)cell_kernel<real, D, 256, 2, 0>;
-        case 4: return (const void*)cell_kernel<real, D, 256, 4, 0>;
-        default: return (const void*)cell_kernel<real, D, 256, 8, 0>;
+        case 1: return (const void*)cell_kernel<real, D, 256, 1, 0, XB>;
+        case 2: return (const void*)cell_kernel<real, D, 256, 2, 0, XB>;
+        case 4: return (const void*)cell_kernel<real, D, 256, 4, 0, XB>;
+        default: return (const void*)cell_kernel<real, D, 256, 8, 0, XB>;
     }
 }
 
@@ -264,7 +289,7 @@ usp_status set_lds(usp_ctx* ctx, const void* kern, size_t lds)
 
 // the kernels of one cell pass with their dynamic LDS sizes
 template <typename F>
-usp_status for_each_tier(int prec, int dim, int max_nb, int first, int top, F f)
+usp_status for_each_tier(int prec, int dim, int xb, int max_nb, int first, int top, F f)
 {
     const int lo = std::min(first, top);
     for (int t = lo; t <= top; ++t) {
@@ -273,16 +298,18 @@ usp_status for_each_tier(int prec, int dim, int max_nb, int first, int top, F f)
         usp_status st = with_kernel(prec, dim, [&](auto* rp, auto dimc) -> usp_status {
             using real = std::remove_pointer_t<decltype(rp)>;
             constexpr int D = decltype(dimc)::value;
-            return f(t, lo, sh, cell_kernel_for<real, D>(sh), lds);
+            return f(t, lo, sh,
+                     xb ? cell_kernel_for<real, D, true>(sh) : cell_kernel_for<real, D, false>(sh),
+                     lds);
         });
         if (st) return st;
     }
     return USP_OK;
 }
 
-usp_status prepare_cell(usp_ctx* ctx, int prec, int dim, int max_nb, int first, int top)
+usp_status prepare_cell(usp_ctx* ctx, int prec, int dim, int xb, int max_nb, int first, int top)
 {
-    return for_each_tier(prec, dim, max_nb, first, top,
+    return for_each_tier(prec, dim, xb, max_nb, first, top,
                          [&](int, int, Shape, const void* kern, size_t lds) {
                              return set_lds(ctx, kern, lds);
                          });
@@ -292,8 +319,8 @@ usp_status prepare_cell(usp_ctx* ctx, int prec, int dim, int max_nb, int first, 
 // Instances that need more particle slots than the 256 x (4 | 6) shape run
 // every cell with it first; a cell that needs more is handed on, untouched,
 // to the 8-slot shape through the tier list.
-usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int max_nb, int first, int top,
-                       hipStream_t stream)
+usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int xb, int max_nb, int first,
+                       int top, hipStream_t stream)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->timing) {
@@ -302,7 +329,7 @@ usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int max_nb, int
         HIPCHK(ctx, hipEventRecord(e0, stream));
     }
     usp_status st = for_each_tier(
-        prec, dim, max_nb, first, top,
+        prec, dim, xb, max_nb, first, top,
         [&](int t, int lo, Shape sh, const void* kern, size_t lds) -> usp_status {
             usp_status s2 = set_lds(ctx, kern, lds);
             if (s2) return s2;
@@ -389,8 +416,8 @@ usp_status finish_state(usp_ctx* ctx, Instance* in)
     usp_status s = ensure_tiers(ctx, B.ncells);
     if (s) return s;
     attach_tiers(ctx, B);
-    if ((s = launch_cell(ctx, B, in->h.prec, in->h.dim, in->h.nb, in->first_shape(), in->top(),
-                         ctx->stream)))
+    if ((s = launch_cell(ctx, B, in->h.prec, in->h.dim, in->xb(), in->h.nb, in->first_shape(),
+                         in->top(), ctx->stream)))
         return s;
     if ((s = launch_fields(ctx, B, 1, ctx->stream))) return s;
     return launch_ctl(ctx, B, 0, ctx->stream);
@@ -481,8 +508,19 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
         h.face_kind[f] = pb->face[f].kind;
         h.face_T[f] = pb->face[f].T;
         for (int k = 0; k < 3; ++k) h.face_u[3 * f + k] = pb->face[f].u[k];
+        h.face_n[f] = pb->face[f].n;
+        h.face_split[f] = pb->face[f].split;
+        h.face_nb[f] = pb->face[f].n_b;
+        h.face_Tb[f] = pb->face[f].T_b;
+        // x faces of a 1-D problem are inert
+        if (pb->face[f].kind == USP_BC_OPEN && (pb->dim == 2 || f >= 2)) h.open_mask |= 1 << f;
     }
     for (int k = 0; k < 3; ++k) h.accel[k] = pb->accel[k];
+    h.plate = pb->plate != 0;
+    h.plate_x = pb->plate_x;
+    h.plate_ylo = pb->plate_ylo;
+    h.plate_yhi = pb->plate_yhi;
+    h.plate_T = pb->plate_T;
     h.dt = nm->dt;
     h.r_p = nm->r_p;
     h.Kn_c = nm->Kn_c;
@@ -660,7 +698,7 @@ namespace {
 // one launch group of a usp_step call: instances of one kernel flavour
 struct Plan {
     Batch B;
-    int prec, dim, max_nb, first, top;
+    int prec, dim, xb, max_nb, first, top;
 };
 
 // groups the instances by kernel flavour (precision, dimension, shape) and
@@ -670,15 +708,17 @@ usp_status make_plan(usp_ctx* ctx, const int* ids, int n_ids, std::vector<Plan>&
 {
     for (int i = 0; i < n_ids; ++i)
         if (!get_inst(ctx, ids[i])) return fail(ctx, USP_ESTATE, "unknown or freed instance in step");
-    // flavour = (precision, dimension, first shape, last shape); the map
-    // keeps the groups in a fixed order
+    // flavour = (precision, dimension, boundary set, first shape, last
+    // shape); the map keeps the groups in a fixed order
     std::map<std::vector<int>, std::vector<int>> flavours;
     for (int i = 0; i < n_ids; ++i) {
         Instance* in = get_inst(ctx, ids[i]);
-        flavours[{in->h.prec, in->h.dim, in->first_shape(), in->top()}].push_back(ids[i]);
+        flavours[{in->h.prec, in->h.dim, in->xb(), in->first_shape(), in->top()}].push_back(
+            ids[i]);
     }
     for (auto& fv : flavours) {
-        const int prec = fv.first[0], dim = fv.first[1], first = fv.first[2], top = fv.first[3];
+        const int prec = fv.first[0], dim = fv.first[1], xb = fv.first[2];
+        const int first = fv.first[3], top = fv.first[4];
         const std::vector<int>& sel = fv.second;
         int ncells = 0, max_nb = 0;
         for (int id : sel) {
@@ -724,10 +764,11 @@ usp_status make_plan(usp_ctx* ctx, const int* ids, int n_ids, std::vector<Plan>&
         P.B.tier_stride = 1 + ncells;
         P.prec = prec;
         P.dim = dim;
+        P.xb = xb;
         P.max_nb = max_nb;
         P.first = first;
         P.top = top;
-        usp_status st = prepare_cell(ctx, prec, dim, max_nb, first, top);
+        usp_status st = prepare_cell(ctx, prec, dim, xb, max_nb, first, top);
         if (st) return st;
         plans.push_back(P);
     }
@@ -740,11 +781,11 @@ usp_status enqueue_group(usp_ctx* ctx, Plan P, int nsteps, hipStream_t st)
 {
     usp_status s;
     P.B.mode = MODE_MOVE;
-    if ((s = launch_cell(ctx, P.B, P.prec, P.dim, P.max_nb, P.first, P.top, st))) return s;
+    if ((s = launch_cell(ctx, P.B, P.prec, P.dim, P.xb, P.max_nb, P.first, P.top, st))) return s;
     if ((s = launch_ctl(ctx, P.B, 0, st))) return s;
     for (int k = 0; k < nsteps; ++k) {
         P.B.mode = k + 1 < nsteps ? (MODE_RELAX | MODE_MOVE) : MODE_RELAX;
-        if ((s = launch_cell(ctx, P.B, P.prec, P.dim, P.max_nb, P.first, P.top, st))) return s;
+        if ((s = launch_cell(ctx, P.B, P.prec, P.dim, P.xb, P.max_nb, P.first, P.top, st))) return s;
         if ((s = launch_fields(ctx, P.B, 0, st))) return s;
         if ((s = launch_ctl(ctx, P.B, 1, st))) return s;
     }

@@ -31,8 +31,10 @@ MU_REF_AR = 2.117e-5
 T_REF_AR = 273.0
 P_ATM = 101325.0
 
-# boundary kinds (same integer codes on both solvers' interfaces)
-BC_DIFFUSE, BC_SPECULAR, BC_PERIODIC = 0, 1, 2
+# boundary kinds (same integer codes on both solvers' interfaces); BC_OPEN is
+# a face to a reservoir: particles leaving through it are gone, and the
+# reservoir's gas enters through it every step
+BC_DIFFUSE, BC_SPECULAR, BC_PERIODIC, BC_OPEN = 0, 1, 2, 3
 # P_ne modes: fixed value, GLL Knudsen number from instantaneous or
 # time-averaged fields (Eq. 16-18)
 PNE_FIXED, PNE_GLL_INST, PNE_GLL_AVG = 0, 1, 2
@@ -78,9 +80,19 @@ class Gas:
 
 @dataclass
 class Face:
+    """A domain face: kind, wall or reservoir temperature T and velocity u
+    (diffuse walls: the wall's; open faces: the reservoir gas's, with no
+    component normal to the face).  Open faces: reservoir number density n;
+    on the part of the face whose tangential coordinate is >= split (2-D),
+    density n_b and temperature T_b instead."""
+
     kind: int = BC_SPECULAR
     T: float = 273.0
     u: Sequence[float] = (0.0, 0.0, 0.0)
+    n: float = 0.0
+    split: float = math.inf
+    n_b: float = 0.0
+    T_b: float = 273.0
 
 
 @dataclass
@@ -127,6 +139,13 @@ class Problem:
     jmom_mode: int = JMOM_INST
     spawn_projection: int = 0
     avg_init: int = 0
+    # internal plate (2-D): a thin diffuse wall at rest at plate_T on the line
+    # x = plate_x for plate_ylo <= y <= plate_yhi
+    plate: int = 0
+    plate_x: float = 0.0
+    plate_ylo: float = 0.0
+    plate_yhi: float = 0.0
+    plate_T: float = 273.0
     meta: dict = field(default_factory=dict)
 
     @property
@@ -138,6 +157,10 @@ class Problem:
 
     def expected_particles(self) -> int:
         return int(np.sum(np.floor(self.init_n * self.vcell / self.Np + 0.5)))
+
+    def _capacity_for(self, ppc: int, factor: float = 3.0) -> "Problem":
+        cap = int(min(2048, max(64, -(-int(factor * ppc) // 64) * 64)))
+        return self.replace(max_ppc=cap)
 
     def with_capacity(self, factor: float = 3.0) -> "Problem":
         """max_ppc = factor x the fullest initial cell (multiple of 64, <= 2048)"""
@@ -213,10 +236,13 @@ def thermal_couette_1d(Kn=1e-3, dT=10.0, T_w=273.0, ncell=1000, ppc=500, dt_over
 
 def sod_1d(Kn=1e-3, L=1.0, ncell=1000, mean_ppc=500, rho_ratio=8.0, p_ratio=10.0,
            T_l=273.0, dt_over_tau=5.0, omega=0.81, precision=32, seed=0,
-           pne_mode=PNE_GLL_INST, jmom_mode=JMOM_AVG, spawn_projection=1,
+           pne_mode=PNE_GLL_INST, jmom_mode=JMOM_AVG, spawn_projection=1, open_ends=False,
            name="sod") -> Problem:
     """Sod shock tube along the resolved axis (Section 4.3), closed by
-    specular ends.  rho_l is chosen so that lambda_l = Kn * L.  At a few
+    specular ends, or with open_ends by open faces to reservoirs holding the
+    initial left and right states (the paper's open boundaries; the waves do
+    not reach the ends before t_final).  rho_l is chosen so that
+    lambda_l = Kn * L.  At a few
     hundred particles per cell and dt = 5 tau_c the instantaneous-moment
     scheme is unstable (the paper used 2.5e4-2e5 particles per cell), so the
     stress and heat flux of the added particles are time-averaged here too."""
@@ -235,8 +261,12 @@ def sod_1d(Kn=1e-3, L=1.0, ncell=1000, mean_ppc=500, rho_ratio=8.0, p_ratio=10.0
     n = np.where(left, n_l, n_r)
     T = np.where(left, T_l, T_r)
     ppc_l = 2.0 * mean_ppc * rho_ratio / (rho_ratio + 1.0)
+    if open_ends:
+        ends = (Face(BC_OPEN, T_l, n=n_l), Face(BC_OPEN, T_r, n=n_r))
+    else:
+        ends = (Face(BC_SPECULAR), Face(BC_SPECULAR))
     return _sized(Problem(name=name, gas=gas, **g,
-                   faces=_faces_1d(Face(BC_SPECULAR), Face(BC_SPECULAR)),
+                   faces=_faces_1d(*ends),
                    accel=(0.0, 0.0, 0.0), dt=dt_over_tau * tau_l, Np=n_l * g["vcell"] / ppc_l,
                    init_n=n, init_u=np.zeros((ncell, 3)), init_T=T, precision=precision,
                    seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
@@ -286,6 +316,64 @@ def cavity_2d(Kn=1e-3, n=128, ppc=200, U_lid=50.0, T_w=273.0, omega=0.81, precis
                    meta=dict(L=L, lam0=lam0, tau0=tau0, n0=n0, U_lid=U_lid, Kn=Kn)))
 
 
+def open_channel_1d(Kn=0.1, ncell=50, ppc=100, n_hi=1.0, T_lo=273.0, T_hi=273.0, omega=0.5,
+                    precision=64, seed=0, empty=False, pne_mode=PNE_GLL_AVG,
+                    jmom_mode=JMOM_AVG, avg_init=1, name="open_channel") -> Problem:
+    """A 1-D channel between two reservoirs: at y = 0 the standard state at
+    T_lo (n0 = p_atm / (k T_lo)), at y = H the density n_hi * n0 at T_hi;
+    H = lambda_0 / Kn, dt = 0.3 dy / mean speed.  The gas starts at the low
+    reservoir's state (or as vacuum with `empty`)."""
+    gas = Gas(omega=omega)
+    n0, rho0, lam0, tau0 = standard_state(gas, T_lo)
+    H = lam0 / Kn
+    g = _grid_1d(ncell, H)
+    lo = Face(BC_OPEN, T_lo, n=n0)
+    hi = Face(BC_OPEN, T_hi, n=n_hi * n0)
+    init_n = np.full(ncell, 0.0 if empty else n0)
+    return _sized(Problem(name=name, gas=gas, **g, faces=_faces_1d(lo, hi),
+                   accel=(0.0, 0.0, 0.0), dt=0.3 * g["dy"] / gas.mean_speed(T_lo),
+                   Np=n0 * g["vcell"] / ppc, init_n=init_n, init_u=np.zeros((ncell, 3)),
+                   init_T=np.full(ncell, T_lo), precision=precision, seed=seed,
+                   pne_mode=pne_mode, jmom_mode=jmom_mode, avg_init=avg_init,
+                   meta=dict(H=H, lam0=lam0, tau0=tau0, n0=n0, Kn=Kn)))._capacity_for(ppc)
+
+
+def slit_2d(Kn=0.01, a_cells=20, ppc=100, p_ratio=2.0, T1=273.0, n1=1.0e20, omega=0.5,
+            precision=32, seed=0, pne_mode=PNE_GLL_AVG, jmom_mode=JMOM_AVG,
+            spawn_projection=0, avg_init=1, name="slit") -> Problem:
+    """Flow through a slit of width a between two chambers (Section 4.5),
+    half domain by the symmetry plane y = 0: x in [-10a, 10a], y in [0, 10a],
+    cell size a / a_cells (400 x 200 cells at a_cells = 20).  A thin diffuse
+    plate at T1 on x = 0 for y >= a/2; specular symmetry plane at y = 0; open
+    faces to the upstream reservoir (n1, T1) on the left and on the top of
+    the left chamber, to the downstream reservoir (n1 / p_ratio, T1) on the
+    right and on the top of the right chamber.  Kn = lambda_1 / a with the
+    Eq. 36 mean free path of the upstream state; hard spheres by default (the
+    paper's slit gas).  The chambers start at their reservoirs' states;
+    ppc is the mean over the domain; dt = 0.3 dx / mean speed."""
+    gas = Gas(omega=omega)
+    n2 = n1 / p_ratio
+    p1 = n1 * gas.kB * T1
+    lam1 = gas.mean_free_path(gas.m * n1, p1, T1)
+    a = lam1 / Kn
+    d = a / a_cells
+    nx, ny = 20 * a_cells, 10 * a_cells
+    xs = -10.0 * a + (np.arange(nx) + 0.5) * d
+    n = np.tile(np.where(xs < 0.0, n1, n2), ny)
+    nc = nx * ny
+    faces = [Face(BC_OPEN, T1, n=n1), Face(BC_OPEN, T1, n=n2), Face(BC_SPECULAR),
+             Face(BC_OPEN, T1, n=n1, split=0.0, n_b=n2, T_b=T1)]
+    return _sized(Problem(name=name, gas=gas, dim=2, nx=nx, ny=ny, x0=-10.0 * a, x1=10.0 * a,
+                   y0=0.0, y1=10.0 * a, dx=d, dy=d, inv_dx=1.0 / d, inv_dy=1.0 / d,
+                   vcell=d * d, faces=faces, accel=(0.0, 0.0, 0.0),
+                   dt=0.3 * d / gas.mean_speed(T1), Np=0.5 * (n1 + n2) * d * d / ppc,
+                   init_n=n, init_u=np.zeros((nc, 3)), init_T=np.full(nc, T1),
+                   precision=precision, seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
+                   spawn_projection=spawn_projection, avg_init=avg_init, plate=1, plate_x=0.0,
+                   plate_ylo=0.5 * a, plate_yhi=10.0 * a, plate_T=T1,
+                   meta=dict(a=a, lam1=lam1, n1=n1, n2=n2, p1=p1, T1=T1, Kn=Kn)))
+
+
 def homogeneous_box(ncell=64, ppc=1000, nu_dt=1.0, T=273.0, precision=64, seed=0,
                     pne=1.0, omega=0.5, name="box") -> Problem:
     """Spatially homogeneous gas in a periodic 1-D box whose cells are
@@ -310,7 +398,7 @@ def _sized(pb: Problem) -> Problem:
 
 def config(name: str, **kw) -> Problem:
     """The named workloads: C1 Couette (FP64), C2 thermal Couette and Sod,
-    C3 cavity at three Kn."""
+    C3 cavity at three Kn, C5 slit at two Kn."""
     if name == "c1":
         return couette_1d(**kw)
     if name == "c2_tc":
@@ -320,4 +408,7 @@ def config(name: str, **kw) -> Problem:
     if name.startswith("c3"):
         kn = {"c3": 1e-3, "c3_kn1e-3": 1e-3, "c3_kn1e-2": 1e-2, "c3_kn1e-1": 0.1}[name]
         return cavity_2d(Kn=kn, **kw)
+    if name.startswith("c5"):
+        kn = {"c5": 0.01, "c5_kn1e-2": 0.01, "c5_kn1e-1": 0.1}[name]
+        return slit_2d(Kn=kn, **kw)
     raise KeyError(name)

@@ -36,14 +36,16 @@ class Gas(C.Structure):
 
 
 class Face(C.Structure):
-    _fields_ = [("kind", C.c_int), ("T", C.c_double), ("u", C.c_double * 3)]
+    _fields_ = [("kind", C.c_int), ("T", C.c_double), ("u", C.c_double * 3), ("n", C.c_double),
+                ("split", C.c_double), ("n_b", C.c_double), ("T_b", C.c_double)]
 
 
 class ProblemC(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int)] + \
                [(n, C.c_double) for n in ("x0", "x1", "y0", "y1", "dx", "dy", "inv_dx",
                                           "inv_dy", "vcell")] + \
-               [("face", Face * 4), ("accel", C.c_double * 3)]
+               [("face", Face * 4), ("accel", C.c_double * 3), ("plate", C.c_int)] + \
+               [(n, C.c_double) for n in ("plate_x", "plate_ylo", "plate_yhi", "plate_T")]
 
 
 class Numerics(C.Structure):
@@ -142,8 +144,11 @@ def to_c(pb):
         p.face[i].T = f.T
         for k in range(3):
             p.face[i].u[k] = f.u[k]
+        p.face[i].n, p.face[i].split, p.face[i].n_b, p.face[i].T_b = f.n, f.split, f.n_b, f.T_b
     for k in range(3):
         p.accel[k] = pb.accel[k]
+    p.plate, p.plate_x, p.plate_ylo, p.plate_yhi, p.plate_T = (pb.plate, pb.plate_x, pb.plate_ylo,
+                                                              pb.plate_yhi, pb.plate_T)
     nm = Numerics()
     for n in ("dt", "Np", "r_p", "Kn_c", "pne_fixed"):
         setattr(nm, n, getattr(pb, n))

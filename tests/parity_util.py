@@ -18,7 +18,7 @@ import numpy as np
 
 from oracle import oracle as O
 
-INT_DIAG = ["n_in", "n4", "n_sel", "n_usp", "n_del", "n7", "n_out", "n2"]
+INT_DIAG = ["n_in", "n4", "n_sel", "n_usp", "n_del", "n7", "n_out", "n2", "n_inj", "n_gone"]
 TIE = 1e-9
 
 

@@ -62,6 +62,14 @@ def test_cavity_full_size(kn):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("kn", [0.01, 0.1])
+def test_slit_full_size(kn):
+    """400 x 200 cells x 100 particles/cell (8 M), FP32, pressure ratio 2:
+    open faces on three sides, the plate, the symmetry plane"""
+    _parity([P.slit_2d(Kn=kn, seed=23)])
+
+
+@pytest.mark.gpu
 def test_couette_c1_full_size():
     """100 cells x 100 particles/cell, FP64, hard spheres, walls +-100 m/s"""
     _parity([P.couette_1d(seed=0)], warm=5)

@@ -67,6 +67,16 @@ def _cases():
         # left state of ~1000 particles per cell: those cells are handed from
         # the 256 x 4 shape to the larger ones, the right state is not
         "sod_fp32_tiers": lambda: P.sod_1d(ncell=64, mean_ppc=560, seed=13),
+        # open faces (reservoirs) and the slit's plate
+        "sod_open_fp32": lambda: P.sod_1d(ncell=150, mean_ppc=200, open_ends=True, seed=14),
+        "open_channel_fp64": lambda: P.open_channel_1d(Kn=0.1, ncell=30, ppc=100, n_hi=0.5,
+                                                       T_hi=320.0, seed=15),
+        "effusion_fp32": lambda: P.open_channel_1d(Kn=1.0, ncell=30, ppc=100, n_hi=0.0,
+                                                   precision=32, seed=16),
+        "slit_fp32": lambda: P.slit_2d(Kn=0.1, a_cells=3, ppc=40, seed=17),
+        "slit_fp64_vacuum": lambda: P.slit_2d(Kn=0.01, a_cells=2, ppc=40, p_ratio=math.inf,
+                                              precision=64, seed=18),
+        "slit_fp32_far": lambda: _window(P.slit_2d(Kn=0.1, a_cells=3, ppc=40, seed=19), 1),
     }
 
 
@@ -159,7 +169,8 @@ def test_cells_handed_to_larger_shapes():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("name", ["c1_couette_fp64", "thermal_couette_fp32", "cavity_fp32"])
+@pytest.mark.parametrize("name", ["c1_couette_fp64", "thermal_couette_fp32", "cavity_fp32",
+                                  "sod_open_fp32", "slit_fp32"])
 def test_multi_step_trajectory(ctx, name):
     """several steps in one call (fused relax + move kernel) against the
     oracle stepping the same number of times; compared while no decision has
@@ -251,7 +262,8 @@ def test_graph_replay_matches_eager():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("name", ["thermal_couette_fp32", "sod_fp32_tiers", "cavity_fp32"])
+@pytest.mark.parametrize("name", ["thermal_couette_fp32", "sod_fp32_tiers", "cavity_fp32",
+                                  "slit_fp32"])
 def test_step_calls_split_anywhere_give_the_same_state(name):
     """k steps in one call (relax of step n fused with the move of step n+1)
     against the same k steps one call each (a relax-only and a move-only pass
