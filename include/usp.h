@@ -231,12 +231,14 @@ usp_status usp_get_shape(usp_ctx* ctx, int id, int* first, int* last, int* nshap
 usp_status usp_set_graph(usp_ctx* ctx, int on);
 
 /* Kernel timing (benchmarking): while on, every pass of the fused cell
- * kernel (all its shape launches) is bracketed by two HIP events on the
- * stream it runs on.
+ * kernel (the launches of all shapes over the cells of one step) is
+ * bracketed by two HIP events on the stream it runs on; the stream is
+ * drained before each pass, so that the pass's launches are queued behind
+ * its start event at once.  Timing mode launches eagerly (no graphs).
  * usp_get_timing synchronises and returns the summed event time of those
- * launches (ms) and their number since timing was switched on. */
+ * passes (ms) and their number since timing was switched on. */
 usp_status usp_set_timing(usp_ctx* ctx, int on);
-usp_status usp_get_timing(usp_ctx* ctx, double* ms, long long* launches);
+usp_status usp_get_timing(usp_ctx* ctx, double* ms, long long* passes);
 
 /* Philox4x32-10 evaluated on the device for n counters (ctr [n][4], out
  * [n][4], host arrays) with key (k0, k1); for checking the generator. */

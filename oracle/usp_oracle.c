@@ -21,7 +21,12 @@
  *           scale of their velocities so that the cell's mass, momentum and
  *           energy equal those of f-tilde^* (the paper does not specify this
  *           correction; the zero collision invariants of J (Eq. 14-15) and of
- *           the ES operator make those totals the right targets);
+ *           the ES operator make those totals the right targets).  A
+ *           correction is only made where it is one: a common weight in
+ *           [1/2, 2], a shift of the mean of at most 3 rms spreads of the
+ *           reassigned velocities, a scale in [1/3, 3]; otherwise that part is
+ *           skipped and counted (with a few particles per cell, a tiny common
+ *           weight would otherwise demand enormous velocities);
  *   step 8  moments of f^{n+1} (Eq. 1), exponential time averaging (Eq. 34)
  *           and P_ne for the next step (Eq. 16-18 with lambda of Eq. 36).
  *
@@ -1010,7 +1015,7 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
             } else {
                 double Wr = (M0 - Mr) / nusp;
                 dg[D_WR] = Wr;
-                if (!(Wr > 0.0)) {
+                if (!(Wr >= 0.5 && Wr <= 2.0)) {
                     flags |= F_FAILMASS;
                 } else {
                     double MR = Wr * nusp;
@@ -1028,19 +1033,30 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
                                 D += e * e;
                             }
                     double a2 = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+                    double da2 = 0.0;
+                    for (int k = 0; k < 3; ++k) da2 += (a[k] - cb[k]) * (a[k] - cb[k]);
                     double s = 1.0;
+                    int shift = 1;
                     if (nusp >= 2 && D > 0.0) {
-                        double s2 = (E0 - Er - 0.5 * MR * a2) / (0.5 * Wr * D);
-                        dg[D_S2] = s2;
-                        if (s2 > 0.0) s = sqrt(s2);
-                        else flags |= F_FAILENERGY;
+                        if (!(da2 <= 9.0 * D / nusp)) {
+                            /* the mean would move by more than 3 rms spreads */
+                            shift = 0;
+                            flags |= F_FAILENERGY;
+                        } else {
+                            double s2 = (E0 - Er - 0.5 * MR * a2) / (0.5 * Wr * D);
+                            dg[D_S2] = s2;
+                            if (s2 >= 1.0 / 9.0 && s2 <= 9.0) s = sqrt(s2);
+                            else flags |= F_FAILENERGY;
+                        }
                     } else {
                         flags |= F_FAILENERGY;
                     }
                     for (int i = 0; i < nl; ++i)
                         if (si[i].fate == 1) {
                             part* q = &L->p[i];
-                            for (int k = 0; k < 3; ++k) q->c[k] = st(g, a[k] + s * (q->c[k] - cb[k]));
+                            if (shift)
+                                for (int k = 0; k < 3; ++k)
+                                    q->c[k] = st(g, a[k] + s * (q->c[k] - cb[k]));
                             q->w = st(g, Wr);
                         }
                 }
@@ -1384,9 +1400,11 @@ static void one_step(uspo* o)
     o->step++;
 }
 
+/* A capacity error is sticky: the instance takes no further steps (its
+ * cells may already hold more particles than the configuration allows). */
 int uspo_step(uspo* o, int nsteps)
 {
-    for (int i = 0; i < nsteps; ++i) one_step(o);
+    for (int i = 0; i < nsteps && o->error == 0; ++i) one_step(o);
     return o->error;
 }
 

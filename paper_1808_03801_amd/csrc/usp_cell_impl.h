@@ -971,7 +971,9 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                     const double M0 = Ms[0];
                     const double Wr = (M0 - cs[0]) / nusp;
                     WrOut = Wr;
-                    if (!(Wr > 0.0)) {
+                    // a correction only where it is one: common weight in
+                    // [1/2, 2], mean shift within 3 rms spreads, scale in [1/3, 3]
+                    if (!(Wr >= 0.5 && Wr <= 2.0)) {
                         flags |= F_FAILMASS;
                     } else {
                         const double MR = Wr * nusp;
@@ -986,21 +988,34 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                         const double D = cs[8] - nusp * (cb[0] * cb[0] + cb[1] * cb[1] +
                                                          cb[2] * cb[2]);
                         const double a2 = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+                        double da2 = 0.0;
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) da2 += (a[q] - cb[q]) * (a[q] - cb[q]);
                         double sc = 1.0;
+                        bool shift = true;
                         if (nusp >= 2 && D > 0.0) {
-                            const double s2 = (Ms[26] - cs[4] - 0.5 * MR * a2) / (0.5 * Wr * D);
-                            s2Out = s2;
-                            if (s2 > 0.0) sc = sqrt(s2);
-                            else flags |= F_FAILENERGY;
+                            if (!(da2 <= 9.0 * D / nusp)) {
+                                // the mean would move by more than 3 rms spreads
+                                shift = false;
+                                flags |= F_FAILENERGY;
+                            } else {
+                                const double s2 =
+                                    (Ms[26] - cs[4] - 0.5 * MR * a2) / (0.5 * Wr * D);
+                                s2Out = s2;
+                                if (s2 >= 1.0 / 9.0 && s2 <= 9.0) sc = sqrt(s2);
+                                else flags |= F_FAILENERGY;
+                            }
                         } else {
                             flags |= F_FAILENERGY;
                         }
 #pragma unroll
                         for (int k = 0; k < PPT; ++k)
                             if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
-                                P.c0[k] = (real)(a[0] + sc * ((double)P.c0[k] - cb[0]));
-                                P.c1[k] = (real)(a[1] + sc * ((double)P.c1[k] - cb[1]));
-                                P.c2[k] = (real)(a[2] + sc * ((double)P.c2[k] - cb[2]));
+                                if (shift) {
+                                    P.c0[k] = (real)(a[0] + sc * ((double)P.c0[k] - cb[0]));
+                                    P.c1[k] = (real)(a[1] + sc * ((double)P.c1[k] - cb[1]));
+                                    P.c2[k] = (real)(a[2] + sc * ((double)P.c2[k] - cb[2]));
+                                }
                                 P.w[k] = (real)Wr;
                             }
                     }

@@ -61,9 +61,10 @@ struct usp_ctx {
     std::string err;
     int block = 256;
     size_t allocated = 0;
-    // kernel timing
+    // kernel timing: a start/stop event pair per cell-kernel launch
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    long long timed_passes = 0;
     // device descriptor tables of launch groups, keyed by their instance ids,
     // with the group's shape-tier lists (NSHAPE x (1 + ncells) ints)
     struct Group {
@@ -322,8 +323,12 @@ usp_status prepare_cell(usp_ctx* ctx, int prec, int dim, int xb, int max_nb, int
 usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int xb, int max_nb, int first,
                        int top, hipStream_t stream)
 {
+    // timing: the stream is drained first, so that the pass's launches are
+    // queued behind its start event at once and nothing but the pass lies
+    // between the two events
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->timing) {
+        HIPCHK(ctx, hipStreamSynchronize(stream));
         HIPCHK(ctx, hipEventCreate(&e0));
         HIPCHK(ctx, hipEventCreate(&e1));
         HIPCHK(ctx, hipEventRecord(e0, stream));
@@ -344,6 +349,7 @@ usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int xb, int max
         HIPCHK(ctx, hipEventRecord(e1, stream));
         ctx->events.emplace_back(e0, e1);
     }
+    if (ctx->timing) ++ctx->timed_passes;
     return USP_OK;
 }
 
@@ -1112,13 +1118,14 @@ usp_status usp_set_timing(usp_ctx* ctx, int on)
         (void)hipEventDestroy(e.second);
     }
     ctx->events.clear();
+    ctx->timed_passes = 0;
     ctx->timing = on != 0;
     return USP_OK;
 }
 
-usp_status usp_get_timing(usp_ctx* ctx, double* ms, long long* launches)
+usp_status usp_get_timing(usp_ctx* ctx, double* ms, long long* passes)
 {
-    if (!ctx || !ms || !launches) return USP_EINVAL;
+    if (!ctx || !ms || !passes) return USP_EINVAL;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     double t = 0.0;
     for (auto& e : ctx->events) {
@@ -1127,7 +1134,7 @@ usp_status usp_get_timing(usp_ctx* ctx, double* ms, long long* launches)
         t += f;
     }
     *ms = t;
-    *launches = (long long)ctx->events.size();
+    *passes = ctx->timed_passes;
     return USP_OK;
 }
 

@@ -189,9 +189,13 @@ def standard_state(gas: Gas, T0: float = 273.0, p0: float = P_ATM):
 
 
 def couette_1d(Kn=0.1, U_w=100.0, T_w=273.0, ncell=100, ppc=100, dt_over_tau=1.0,
-               omega=0.5, precision=64, seed=0, pne_mode=PNE_GLL_AVG, name="couette") -> Problem:
+               omega=0.5, precision=64, seed=0, pne_mode=PNE_GLL_AVG, jmom_mode=JMOM_AVG,
+               avg_init=1, name="couette") -> Problem:
     """Planar Couette flow between diffuse plates moving at -U_w (bottom) and
-    +U_w (top) along x (Section 4.1); Kn = lambda_0 / H."""
+    +U_w (top) along x (Section 4.1); Kn = lambda_0 / H.  The added particles
+    and the ES target take sigma and q from the Eq. 34 averages started at
+    the initial state (with instantaneous moments, 100 particles per cell
+    overflow a cell's capacity within a hundred steps)."""
     gas = Gas(omega=omega)
     n0, rho0, lam0, tau0 = standard_state(gas, T_w)
     H = lam0 / Kn
@@ -202,7 +206,7 @@ def couette_1d(Kn=0.1, U_w=100.0, T_w=273.0, ncell=100, ppc=100, dt_over_tau=1.0
                    accel=(0.0, 0.0, 0.0), dt=dt_over_tau * tau0, Np=n0 * g["vcell"] / ppc,
                    init_n=np.full(ncell, n0), init_u=np.zeros((ncell, 3)),
                    init_T=np.full(ncell, T_w), precision=precision, seed=seed,
-                   pne_mode=pne_mode,
+                   pne_mode=pne_mode, jmom_mode=jmom_mode, avg_init=avg_init,
                    meta=dict(H=H, lam0=lam0, tau0=tau0, n0=n0, U_w=U_w, T_w=T_w, Kn=Kn)))
 
 

@@ -70,7 +70,7 @@ def build_problem(req: Request) -> P.Problem:
     if req.kind == "couette":
         pb = P.couette_1d(Kn=req.Kn, U_w=50.0, ncell=req.ncell, ppc=req.ppc, dt_over_tau=dto,
                           omega=0.81, precision=32, seed=req.seed)
-        pb = pb.replace(jmom_mode=P.JMOM_AVG, spawn_projection=1)
+        pb = pb.replace(jmom_mode=P.JMOM_AVG, spawn_projection=1, avg_init=0)
     elif req.kind == "poiseuille":
         gas = P.Gas(omega=0.81)
         lam0 = P.standard_state(gas, 273.0)[2]

@@ -265,7 +265,7 @@ class Context:
         _check(self.h, lib().usp_set_graph(self.h, int(on)))
 
     def timing(self):
-        """(summed fused-kernel event time in ms, number of launches)"""
+        """(summed cell-kernel time in ms, number of cell passes)"""
         ms, n = C.c_double(), C.c_longlong()
         _check(self.h, lib().usp_get_timing(self.h, C.byref(ms), C.byref(n)))
         return ms.value, n.value

@@ -48,6 +48,8 @@ def ctx():
 def _cases():
     return {
         "c1_couette_fp64": lambda: P.couette_1d(ncell=40, ppc=100, seed=3),
+        "couette_fp64_inst": lambda: P.couette_1d(ncell=40, ppc=100, seed=24,
+                                                  jmom_mode=P.JMOM_INST, avg_init=0),
         "couette_fp32_avg": lambda: P.couette_1d(ncell=60, ppc=120, Kn=0.02, U_w=150.0,
                                                  dt_over_tau=3.0, precision=32, seed=4).replace(
             jmom_mode=P.JMOM_AVG, spawn_projection=1),
@@ -322,5 +324,33 @@ def test_every_launch_shape_and_the_autotuner_give_the_same_state():
             assert np.array_equal(s0.cells, sx.cells), x.shape()
         with pytest.raises(usp.UspError):
             ref.set_shape(last + 1)
+    finally:
+        c.close()
+
+
+
+@pytest.mark.gpu
+def test_pass_timing():
+    """timing mode: one start/stop pair per cell pass (a call of k steps has
+    k + 1 passes), positive times, and the timed steps leave the state
+    bit-identical to untimed graph replays"""
+    usp = _gpu()
+    pb = _cases()["thermal_couette_fp32"]()
+    c = usp.Context(0)
+    try:
+        c.set_graph(True)
+        a, b = c.add(pb), c.add(pb)
+        c.step([a], 6)
+        c.set_timing(True)
+        for _ in range(3):
+            c.step([b], 2)
+        ms, n = c.timing()
+        c.set_timing(False)
+        c.sync()
+        assert n == 9 and ms > 0.0
+        sa, sb = a.get_state(), b.get_state()
+        assert np.array_equal(sa.counts, sb.counts)
+        assert np.array_equal(sa.parts, sb.parts)
+        assert np.array_equal(sa.cells, sb.cells)
     finally:
         c.close()

@@ -132,7 +132,7 @@ def test_argon_standard_state_numbers():
 def test_first_average_equals_instantaneous_fields():
     # Eq. 34 starts from the first sample; fields derived from averaged raw
     # sums must then equal those from the two-pass centred moments.
-    pb = P.couette_1d(ncell=20, ppc=50, U_w=200.0)
+    pb = P.couette_1d(ncell=20, ppc=50, U_w=200.0, avg_init=0)
     o = O.Oracle(pb)
     o.step(1)
     a, b = o.fields(0), o.fields(1)

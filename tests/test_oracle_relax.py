@@ -135,7 +135,7 @@ def test_per_cell_conservation(precision, jmom, Kn):
     # and after (f^{n+1}) the relaxation, except in counted fallback cells
     pb = P.couette_1d(ncell=60, ppc=120, U_w=150.0, Kn=Kn, dt_over_tau=3.0,
                       precision=precision, seed=9)
-    pb = pb.replace(jmom_mode=jmom, spawn_projection=int(jmom == P.JMOM_AVG))
+    pb = pb.replace(jmom_mode=jmom, spawn_projection=int(jmom == P.JMOM_AVG), avg_init=0)
     o = O.Oracle(pb)
     o.step(5)
     tol = 1e-12 if precision == 64 else 3e-6

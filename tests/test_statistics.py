@@ -1,0 +1,104 @@
+"""Time-averaged profiles: the GPU path against the oracle within 3
+statistical sigma (tests/stat_util.py: batch means over 20 batches).
+
+Steady, rarefied workloads, where the flow forgets its state within a few
+dozen steps (batches of 60 steps are long against that): C1 Couette (FP64,
+and the same in FP32), a 16 x 16 cavity and a small slit at Kn = 0.1.  The
+GPU and the oracle start from the same state; their trajectories part once
+an FP32 rounding flips a decision, and from then on they are two
+statistically equivalent runs.
+
+The comparison itself is pinned on the CPU: two oracle runs with different
+seeds pass it, and a 10 K change of one wall temperature fails it.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1808_03801_amd import problems as P
+from tests.stat_util import check_profiles, z_scores
+
+WARM, STEPS = 200, 1200
+FIELDS_1D = dict(rho=1, u_x=2, T=5, sigma_xy=10, q_y=14)
+FIELDS_2D = dict(rho=1, u_x=2, u_y=3, T=5, sigma_xy=10)
+
+
+def _oracle_run(pb):
+    o = O.Oracle(pb)
+    o.step(WARM)
+    out = []
+    for _ in range(STEPS):
+        o.step(1)
+        out.append(o.fields(0))
+    assert o.error == 0
+    return np.array(out)
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_c1(seed, T_top=273.0):
+    pb = P.couette_1d(seed=seed)
+    if T_top != 273.0:
+        f = list(pb.faces)
+        f[3] = P.Face(P.BC_DIFFUSE, T_top, f[3].u)
+        pb = pb.replace(faces=f)
+    return _oracle_run(pb)
+
+
+def _shape_rho(f):
+    """density relative to the domain mean of the same step: the total mass
+    of a domain without open faces random-walks with the unprojected added
+    batches, differently in every run, and that offset is not a profile
+    difference"""
+    g = f.copy()
+    g[:, :, 1] = f[:, :, 1] / f[:, :, 1].mean(axis=1, keepdims=True)
+    return g
+
+
+def _compare(a, b, fields, frac=0.95):
+    idx = list(fields.values())
+    z, *_ = z_scores(_shape_rho(a)[:, :, idx], _shape_rho(b)[:, :, idx])
+    return check_profiles(z, list(fields.keys()), frac_within=frac)
+
+
+def test_two_oracle_seeds_agree_within_3_sigma():
+    rep = _compare(_oracle_c1(1), _oracle_c1(2), FIELDS_1D)
+    print(rep)
+
+
+def test_a_changed_wall_temperature_is_detected():
+    with pytest.raises(AssertionError):
+        _compare(_oracle_c1(1), _oracle_c1(2, T_top=283.0), FIELDS_1D)
+
+
+def _cases():
+    return {
+        "c1_fp64": lambda: P.couette_1d(seed=1),
+        "c1_fp32": lambda: P.couette_1d(seed=1, precision=32),
+        "cavity_kn0.1": lambda: P.cavity_2d(Kn=0.1, n=16, ppc=80, seed=1),
+        "slit_kn0.1": lambda: P.slit_2d(Kn=0.1, a_cells=2, ppc=30, seed=1),
+    }
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", list(_cases().keys()))
+def test_gpu_time_averaged_profiles_match_the_oracle(name):
+    from paper_1808_03801_amd import usp
+    pb = _cases()[name]()
+    ref = _oracle_run(pb)
+    ctx = usp.Context(0)
+    try:
+        g = ctx.add(pb)
+        ctx.step([g], WARM)
+        out = []
+        for _ in range(STEPS):
+            ctx.step([g], 1)
+            out.append(g.fields(0))
+        ctx.sync()
+        assert g.status() == 0
+        gpu = np.array(out)
+    finally:
+        ctx.close()
+    rep = _compare(gpu, ref, FIELDS_2D if pb.dim == 2 else FIELDS_1D)
+    print(name, rep)
