@@ -344,7 +344,8 @@ def open_channel_1d(Kn=0.1, ncell=50, ppc=100, n_hi=1.0, T_lo=273.0, T_hi=273.0,
 
 def slit_2d(Kn=0.01, a_cells=20, ppc=100, p_ratio=2.0, T1=273.0, n1=1.0e20, omega=0.5,
             precision=32, seed=0, pne_mode=PNE_GLL_AVG, jmom_mode=JMOM_AVG,
-            spawn_projection=0, avg_init=1, name="slit") -> Problem:
+            spawn_projection=0, avg_init=1, n_avg=300, weight_mode=WEIGHT_LITERAL,
+            name="slit") -> Problem:
     """Flow through a slit of width a between two chambers (Section 4.5),
     half domain by the symmetry plane y = 0: x in [-10a, 10a], y in [0, 10a],
     cell size a / a_cells (400 x 200 cells at a_cells = 20).  A thin diffuse
@@ -354,7 +355,15 @@ def slit_2d(Kn=0.01, a_cells=20, ppc=100, p_ratio=2.0, T1=273.0, n1=1.0e20, omeg
     right and on the top of the right chamber.  Kn = lambda_1 / a with the
     Eq. 36 mean free path of the upstream state; hard spheres by default (the
     paper's slit gas).  The chambers start at their reservoirs' states;
-    ppc is the mean over the domain; dt = 0.3 dx / mean speed."""
+    ppc is the mean over the domain; dt = 0.3 dx / mean speed (nu_ES dt =
+    0.08 at Kn = 0.1 and 0.8 at Kn = 0.01).  Added-particle weights as Eq. 26
+    prints them: with the consistent weights (1 / (nu_ES dt) larger) the
+    conservation correction of those heavy particles heats the downstream
+    jet (at Kn = 0.1 its chamber reached 700 K mean and lost half its mass
+    in 3000 steps; at Kn = 0.01 cells on the axis overflowed).  The jet forms
+    over the first thousand steps, so the Eq. 34 averages that feed the added
+    particles use a window of 300 steps (100 is too noisy at 100 particles
+    per cell)."""
     gas = Gas(omega=omega)
     n2 = n1 / p_ratio
     p1 = n1 * gas.kB * T1
@@ -373,7 +382,8 @@ def slit_2d(Kn=0.01, a_cells=20, ppc=100, p_ratio=2.0, T1=273.0, n1=1.0e20, omeg
                    dt=0.3 * d / gas.mean_speed(T1), Np=0.5 * (n1 + n2) * d * d / ppc,
                    init_n=n, init_u=np.zeros((nc, 3)), init_T=np.full(nc, T1),
                    precision=precision, seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
-                   spawn_projection=spawn_projection, avg_init=avg_init, plate=1, plate_x=0.0,
+                   spawn_projection=spawn_projection, avg_init=avg_init, n_avg=n_avg,
+                   weight_mode=weight_mode, plate=1, plate_x=0.0,
                    plate_ylo=0.5 * a, plate_yhi=10.0 * a, plate_T=T1,
                    meta=dict(a=a, lam1=lam1, n1=n1, n2=n2, p1=p1, T1=T1, Kn=Kn)))
 

@@ -73,3 +73,44 @@ def test_slit_full_size(kn):
 def test_couette_c1_full_size():
     """100 cells x 100 particles/cell, FP64, hard spheres, walls +-100 m/s"""
     _parity([P.couette_1d(seed=0)], warm=5)
+
+
+def _long_run(pbs, steps):
+    from paper_1808_03801_amd import usp
+    ctx = usp.Context(0)
+    try:
+        ctx.set_graph(True)
+        gs = [ctx.add(pb) for pb in pbs]
+        n0 = [g.num_particles() for g in gs]
+        left = steps
+        while left > 0:
+            k = min(100, left)
+            ctx.step(gs, k)
+            left -= k
+        ctx.sync()
+        for pb, g, n in zip(pbs, gs, n0):
+            assert g.status() == 0, (pb.name, g.status())
+            f = g.fields(0)
+            assert np.all(np.isfinite(f)), pb.name
+            ratio = g.num_particles() / n
+            T = f[:, 5]
+            print(pb.name, steps, "steps: particles x%.3f, T %.1f..%.1f K" % (ratio, T.min(), T.max()))
+            assert 0.5 < ratio < 2.0
+            assert T.min() > 50.0 and T.max() < 2000.0
+    finally:
+        ctx.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("which", ["c1", "c2", "c3", "c5"])
+def test_workloads_stay_healthy_over_long_runs(which):
+    """every configuration at full size for thousands of steps: no capacity
+    or window error, finite fields, particle count and temperatures in range"""
+    if which == "c1":
+        _long_run([P.couette_1d(seed=0)], 1000)
+    elif which == "c2":
+        _long_run(bench.workload(), 5000)
+    elif which == "c3":
+        _long_run([P.cavity_2d(Kn=kn, seed=31) for kn in (1e-3, 1e-2, 0.1)], 2000)
+    else:
+        _long_run([P.slit_2d(Kn=kn, seed=32) for kn in (0.01, 0.1)], 3000)
