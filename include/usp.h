@@ -56,6 +56,7 @@ enum { USP_PNE_FIXED = 0, USP_PNE_GLL_INST = 1, USP_PNE_GLL_AVG = 2 };
 enum { USP_WEIGHT_CONSISTENT = 0, USP_WEIGHT_LITERAL = 1 };
 enum { USP_CONSERVE_FULL = 0, USP_CONSERVE_NONE = 1 };
 enum { USP_JMOM_INST = 0, USP_JMOM_AVG = 1 };
+enum { USP_SCHEME_USP = 0, USP_SCHEME_SP = 1 };
 
 /* Gas (Section 4): Eq. 35 viscosity mu = mu_ref (T / T_ref)^omega; Pr of
  * Eq. 6 (nu_ES = Pr nu); molecular mass m and Boltzmann constant kB. */
@@ -117,13 +118,21 @@ typedef struct {
  * initial state); avg_init: start of the Eq. 34 averages (both the averaged
  * fields and the averages of f-tilde^* that jmom_mode uses): 0 = the first
  * sample, then a running mean until n_avg samples; 1 = the exact raw moments
- * of the initial Maxwellian state, then the fixed window n_avg. */
+ * of the initial Maxwellian state, then the fixed window n_avg.
+ * scheme: USP_SCHEME_USP (Table 2, the default) or USP_SCHEME_SP, the
+ * SP-ESBGK baseline of Table 1: no added particles (requires pne_mode
+ * USP_PNE_FIXED with pne_fixed = 0), the Eq. 9 count of particles (nearest
+ * integer of N_c (1 - exp(-nu_ES dt)), the smallest rank keys of the cell)
+ * reassigned and none deleted, their velocities a Maxwellian thermal
+ * velocity mapped by Eq. 11 (S = I - (1 - Pr) / (2 Pr) sigma / p) around the
+ * cell's velocity; the conservation correction as for USP. */
 typedef struct {
     double dt, Np, r_p, Kn_c, pne_fixed;
     int pne_mode, n_avg, avg_start, precision, weight_mode, conserve_mode, max_ppc;
     int jmom_mode, spawn_projection, window;
     uint64_t seed;
     int avg_init;
+    int scheme;
 } usp_numerics;
 
 /* Device binding.  alloc/free: device allocator (NULL = hipMalloc/hipFree);

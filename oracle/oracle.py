@@ -43,7 +43,7 @@ class Config(C.Structure):
         ("face_n", C.c_double * 4), ("face_split", C.c_double * 4), ("face_nb", C.c_double * 4),
         ("face_Tb", C.c_double * 4),
         ("plate", C.c_int), ("plate_x", C.c_double), ("plate_ylo", C.c_double),
-        ("plate_yhi", C.c_double), ("plate_T", C.c_double),
+        ("plate_yhi", C.c_double), ("plate_T", C.c_double), ("scheme", C.c_int),
     ]
 
 
@@ -111,6 +111,7 @@ def make_config(pb) -> Config:
         g.face_n[i], g.face_split[i], g.face_nb[i], g.face_Tb[i] = f.n, f.split, f.n_b, f.T_b
     g.plate, g.plate_x, g.plate_ylo, g.plate_yhi, g.plate_T = (pb.plate, pb.plate_x, pb.plate_ylo,
                                                               pb.plate_yhi, pb.plate_T)
+    g.scheme = pb.scheme
     for k in range(3):
         g.accel[k] = pb.accel[k]
     g.dt, g.Np, g.r_p, g.Kn_c, g.pne_fixed = pb.dt, pb.Np, pb.r_p, pb.Kn_c, pb.pne_fixed

@@ -38,6 +38,12 @@
  * Bernoulli trial at the rate of Eq. 9; the particles kept by Eq. 28 are the
  * selected ones with the smallest random rank keys.
  *
+ * The SP-ESBGK baseline of Table 1 (scheme 1) is the same step with P_ne
+ * fixed at 0 (no added particles, Eq. 33 divisors 1), N_s of Eq. 9 particles
+ * (the smallest rank keys of the cell) reassigned and none deleted, and
+ * velocities from the fixed target f_G of the cell through the linear map of
+ * Eq. 10-11 instead of f_G(t).
+ *
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), keyed by
  * the 64-bit seed, counter = (step, purpose << 24 | sub, cell, slot).
  */
@@ -834,10 +840,34 @@ static void totals(const part* p, int n, double* M, double P[3], double* E)
  * lambda(t) = theta (I + (1 - 1/Pr) alpha(t) s*), alpha = P + (1-P) e^{-nu t};
  * velocity u* + L z with L the Cholesky factor of lambda.  A pivot not above
  * 1e-12 theta falls back to the isotropic factor sqrt(theta) I. */
+/* SP-ESBGK (Table 1, steps 3-4): a Maxwellian thermal velocity at the
+ * cell's temperature (Eq. 10) mapped by S = I - (1 - Pr) / (2 Pr) (p_ij /
+ * (rho theta) - I) (Eq. 11), where p_ij / (rho theta) - I = sigma / p. */
+static void resample_sp(const uspo* o, const cellf* f, int cell, int slot, part* q)
+{
+    const uspo_config* g = &o->g;
+    double k = (1.0 - g->Pr) / (2.0 * g->Pr);
+    double S00 = 1.0 - k * f->s[0], S11 = 1.0 - k * f->s[1], S22 = 1.0 - k * f->s[2];
+    double S01 = -k * f->s[3], S02 = -k * f->s[4], S12 = -k * f->s[5];
+    uint32_t r[4];
+    draw(g, (uint32_t)o->step, PUR_RESAMPLE, 0, (uint32_t)cell, (uint32_t)slot, r);
+    double z[3];
+    uspo_normal3(r, g->precision, z);
+    double sq = sqrt(f->theta);
+    q->c[0] = st(g, f->U[0] + sq * (S00 * z[0] + S01 * z[1] + S02 * z[2]));
+    q->c[1] = st(g, f->U[1] + sq * (S01 * z[0] + S11 * z[1] + S12 * z[2]));
+    q->c[2] = st(g, f->U[2] + sq * (S02 * z[0] + S12 * z[1] + S22 * z[2]));
+    q->w = 1.0;
+}
+
 static int resample(const uspo* o, const cellf* f, double pne, int cell, int slot, double ut,
                     part* q)
 {
     const uspo_config* g = &o->g;
+    if (g->scheme == 1) {
+        resample_sp(o, f, cell, slot, q);
+        return 0;
+    }
     double t = uspo_time_sample(ut, f->x, g->Pr * f->nu, g->dt);
     double alpha = pne + (1.0 - pne) * exp(-f->nu * t);
     double c = (1.0 - 1.0 / g->Pr) * alpha;
@@ -942,7 +972,9 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
         int nl = L->n;
         if (nl > g->max_ppc) o->error = -3;
 
-        /* step 5: Bernoulli selection with probability 1 - exp(-nu_ES dt) */
+        /* step 5: Bernoulli selection with probability 1 - exp(-nu_ES dt);
+         * SP-ESBGK: every particle is a candidate and Eq. 9 fixes how many
+         * of them are reassigned (S = N_c (1 - exp(-nu_ES dt))) */
         double psel = -expm1(-f.x);
         dg[D_PSEL] = psel;
         selinfo* si = (selinfo*)calloc((size_t)nl + 1, sizeof(selinfo));
@@ -952,9 +984,9 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
             uint32_t r[4];
             draw(g, (uint32_t)o->step, PUR_SELECT, 0, (uint32_t)d, (uint32_t)i, r);
             double u = uspo_uniform(r[0], g->precision);
-            si[i].sel = u < psel;
+            si[i].sel = g->scheme == 1 ? 1 : u < psel;
             double mg = fabs(u - psel);
-            if (mg < dg[D_MARG_SEL]) dg[D_MARG_SEL] = mg;
+            if (g->scheme != 1 && mg < dg[D_MARG_SEL]) dg[D_MARG_SEL] = mg;
             si[i].rank = (r[1] & 0xFFFFF800u) | (uint32_t)i;
             si[i].ut = uspo_uniform(r[2], g->precision);
             if (si[i].sel) {
@@ -962,7 +994,9 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
                 ++ns;
             }
         }
-        /* Eq. 28: int() = nearest integer, clamped to [0, N_s] */
+        if (g->scheme == 1) S = (double)ns * psel;
+        /* Eq. 28 (Eq. 9 for SP-ESBGK): int() = nearest integer, clamped to
+         * [0, N_s] */
         int nusp = (int)floor(S + 0.5);
         dg[D_MARG_ROUND] = fabs(S - (floor(S) + 0.5));
         if (nusp < 0) nusp = 0;
@@ -970,7 +1004,7 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
         dg[D_SSEL] = S;
         dg[D_NSEL] = ns;
         dg[D_NUSP] = nusp;
-        dg[D_NDEL] = ns - nusp;
+        dg[D_NDEL] = g->scheme == 1 ? 0 : ns - nusp;
         /* keep the nusp selected particles with the smallest rank keys */
         uint32_t* keys = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)ns + 1));
         int j = 0;
@@ -981,7 +1015,8 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
         free(keys);
         for (int i = 0; i < nl; ++i) {
             if (!si[i].sel) si[i].fate = 0;
-            else si[i].fate = (nusp > 0 && si[i].rank <= thr) ? 1 : 2;
+            else if (nusp > 0 && si[i].rank <= thr) si[i].fate = 1;
+            else si[i].fate = g->scheme == 1 ? 0 : 2; /* SP-ESBGK deletes none */
         }
 
         /* step 6 */
@@ -1218,6 +1253,9 @@ static int check_config(const uspo_config* g)
         if (g->dim != 2 || !(g->plate_x > g->x0 && g->plate_x < g->x1)) return -1;
         if (!(g->plate_ylo <= g->plate_yhi) || !(g->plate_T > 0.0)) return -1;
     }
+    if (g->scheme != 0 && g->scheme != 1) return -1;
+    /* SP-ESBGK has no added particles: P_ne fixed at 0 */
+    if (g->scheme == 1 && !(g->pne_mode == 0 && g->pne_fixed == 0.0)) return -1;
     return 0;
 }
 

@@ -59,6 +59,10 @@ typedef struct {
      * plate_ylo <= y <= plate_yhi; both sides reflect */
     int plate;
     double plate_x, plate_ylo, plate_yhi, plate_T;
+    /* 0: USP-ESBGK (Table 2); 1: SP-ESBGK (Table 1): no added particles
+     * (P_ne fixed at 0), N_s of Eq. 9 particles reassigned, velocities from
+     * the fixed target f_G of the cell through the linear map of Eq. 10-11 */
+    int scheme;
 } uspo_config;
 
 /* per-cell state record: centred moments, raw sums, averaged raw sums of f^n,

@@ -436,6 +436,29 @@ __device__ __forceinline__ int resample_one(const InstDev& I, int cell, int slot
                                             real& c1, real& c2)
 {
     uint32_t r[4];
+    if (I.scheme == 1) {
+        // SP-ESBGK (Eq. 10-11): Maxwellian thermal velocity mapped by
+        // S = I - (1 - Pr) / (2 Pr) sigma / p around the cell's velocity
+        const double kk = (1.0 - I.Pr) / (2.0 * I.Pr);
+        const double S00 = 1.0 - kk * f.s[0], S11 = 1.0 - kk * f.s[1], S22 = 1.0 - kk * f.s[2];
+        const double S01 = -kk * f.s[3], S02 = -kk * f.s[4], S12 = -kk * f.s[5];
+        draw(I, step, PUR_RESAMPLE, 0u, (uint32_t)cell, (uint32_t)slot, r);
+        double z[3];
+        if (sizeof(real) == 4) {
+            float zf[3];
+            normal3_f(r, zf);
+            z[0] = zf[0];
+            z[1] = zf[1];
+            z[2] = zf[2];
+        } else {
+            normal3_d(r, I.prec, z);
+        }
+        const double sq = sqrt(f.theta);
+        c0 = (real)(f.U[0] + sq * (S00 * z[0] + S01 * z[1] + S02 * z[2]));
+        c1 = (real)(f.U[1] + sq * (S01 * z[0] + S11 * z[1] + S12 * z[2]));
+        c2 = (real)(f.U[2] + sq * (S02 * z[0] + S12 * z[1] + S22 * z[2]));
+        return 0;
+    }
     r[2] = rt;
     double alpha;
     if (sizeof(real) == 4) {
@@ -881,6 +904,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             const int nl = n0 + n4;
             mark(2);
             // step 5
+            const bool sp = I.scheme == 1;
             const double psel = -expm1(-f.x);
             double ss[2] = {0.0, 0.0};
             double msel = __builtin_inf();
@@ -893,8 +917,9 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                     uint32_t r[4];
                     draw(I, step, PUR_SELECT, 0u, (uint32_t)c, (uint32_t)j, r);
                     const double u = uni_d(r[0], I.prec);
-                    const bool sel = u < psel;
-                    msel = fmin(msel, fabs(u - psel));
+                    // SP-ESBGK: every particle is a candidate (Eq. 9 counts them)
+                    const bool sel = sp || u < psel;
+                    if (!sp) msel = fmin(msel, fabs(u - psel));
                     P.key[k] = (r[1] & 0xFFFFF800u) | (uint32_t)j;
                     rtime[k] = r[2];
                     if (sel) {
@@ -906,8 +931,9 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             }
             bsum<NT>(ss, L.red, tid);
             if (dg) msel = bmin<NT>(msel, L.red, tid);
-            const double S = ss[0];
             const int ns = (int)ss[1];
+            // Eq. 28; for SP-ESBGK Eq. 9: N_c (1 - exp(-nu_ES dt))
+            const double S = sp ? (double)ns * psel : ss[0];
             int nusp = (int)floor(S + 0.5);
             if (nusp < 0) nusp = 0;
             if (nusp > ns) nusp = ns;
@@ -918,8 +944,9 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             for (int k = 0; k < PPT; ++k)
                 if (k * NT < nlu && fate(P, k) == FT_SEL)
                     P.st[k] = (P.st[k] & ~0xFFu) |
-                              ((nusp == ns || (nusp > 0 && P.key[k] <= thr)) ? FT_REASSIGN
-                                                                             : FT_DELETE);
+                              ((nusp == ns || (nusp > 0 && P.key[k] <= thr))
+                                   ? FT_REASSIGN
+                                   : (sp ? FT_KEEP : FT_DELETE));
             mark(4);
             // step 6
             double fbs[1] = {0.0};
@@ -1045,7 +1072,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                 dg[D_SSEL] = S;
                 dg[D_NSEL] = ns;
                 dg[D_NUSP] = nusp;
-                dg[D_NDEL] = ns - nusp;
+                dg[D_NDEL] = sp ? 0 : ns - nusp;
                 dg[D_N7] = n7;
                 dg[D_CHOLFB] = fbt[0];
                 dg[D_MARG_CNT] = mcnt;

@@ -206,6 +206,10 @@ usp_status validate(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb, con
         return fail(ctx, USP_EINVAL, "a periodic face needs a periodic opposite face");
     if (open && (pb->accel[0] != 0.0 || pb->accel[1] != 0.0 || pb->accel[2] != 0.0))
         return fail(ctx, USP_EINVAL, "open faces cannot be combined with a body acceleration");
+    if (nm->scheme != USP_SCHEME_USP && nm->scheme != USP_SCHEME_SP)
+        return fail(ctx, USP_EINVAL, "unknown scheme");
+    if (nm->scheme == USP_SCHEME_SP && !(nm->pne_mode == USP_PNE_FIXED && nm->pne_fixed == 0.0))
+        return fail(ctx, USP_EINVAL, "SP-ESBGK needs pne_mode FIXED with pne_fixed 0");
     if (pb->plate) {
         if (pb->dim != 2 || !(pb->plate_x > pb->x0 && pb->plate_x < pb->x1))
             return fail(ctx, USP_EINVAL, "plate needs 2-D and x0 < plate_x < x1");
@@ -541,6 +545,7 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
     h.jmom_mode = nm->jmom_mode;
     h.proj = nm->spawn_projection;
     h.avg_init = nm->avg_init != 0;
+    h.scheme = nm->scheme;
     h.key0 = (uint32_t)(nm->seed & 0xFFFFFFFFu);
     h.key1 = (uint32_t)(nm->seed >> 32);
     Window w = choose_window(gas, pb, nm, init_u, init_T);

@@ -47,6 +47,9 @@ CONSERVE_FULL, CONSERVE_NONE = 0, 1
 # (Eq. 1) or exponentially time-averaged (Eq. 34, steady flows)
 JMOM_INST, JMOM_AVG = 0, 1
 
+# the per-step scheme: USP-ESBGK (Table 2) or the SP-ESBGK baseline (Table 1)
+SCHEME_USP, SCHEME_SP = 0, 1
+
 FACE_XLO, FACE_XHI, FACE_YLO, FACE_YHI = 0, 1, 2, 3
 
 
@@ -146,6 +149,7 @@ class Problem:
     plate_ylo: float = 0.0
     plate_yhi: float = 0.0
     plate_T: float = 273.0
+    scheme: int = SCHEME_USP
     meta: dict = field(default_factory=dict)
 
     @property
@@ -404,6 +408,14 @@ def homogeneous_box(ncell=64, ppc=1000, nu_dt=1.0, T=273.0, precision=64, seed=0
                    init_T=np.full(ncell, T), precision=precision, seed=seed,
                    pne_mode=PNE_FIXED, pne_fixed=pne,
                    meta=dict(n0=n0, nu=nu, tau0=tau0, lam0=lam0, H=H)))
+
+
+def sp_esbgk(pb: Problem) -> Problem:
+    """The same problem under the SP-ESBGK baseline (Table 1): no added
+    particles (P_ne fixed at 0), the Eq. 9 count of particles reassigned,
+    velocities through the linear map of Eq. 10-11."""
+    return pb.replace(scheme=SCHEME_SP, pne_mode=PNE_FIXED, pne_fixed=0.0,
+                      name=pb.name + "_sp")
 
 
 def _sized(pb: Problem) -> Problem:

@@ -79,6 +79,10 @@ def _cases():
         "slit_fp64_vacuum": lambda: P.slit_2d(Kn=0.01, a_cells=2, ppc=40, p_ratio=math.inf,
                                               precision=64, seed=18),
         "slit_fp32_far": lambda: _window(P.slit_2d(Kn=0.1, a_cells=3, ppc=40, seed=19), 1),
+        # the SP-ESBGK baseline (Table 1)
+        "c1_sp_fp64": lambda: P.sp_esbgk(P.couette_1d(ncell=40, ppc=100, seed=25)),
+        "cavity_sp_fp32": lambda: P.sp_esbgk(P.cavity_2d(Kn=0.01, n=16, ppc=80, seed=26)),
+        "sod_sp_fp32": lambda: P.sp_esbgk(P.sod_1d(ncell=150, mean_ppc=200, seed=27)),
     }
 
 
@@ -172,7 +176,7 @@ def test_cells_handed_to_larger_shapes():
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("name", ["c1_couette_fp64", "thermal_couette_fp32", "cavity_fp32",
-                                  "sod_open_fp32", "slit_fp32"])
+                                  "sod_open_fp32", "slit_fp32", "cavity_sp_fp32"])
 def test_multi_step_trajectory(ctx, name):
     """several steps in one call (fused relax + move kernel) against the
     oracle stepping the same number of times; compared while no decision has
