@@ -1423,7 +1423,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
 }
 
 template <typename real, int DIM, int NT, int PPT, int PPT2, bool XB>
-__global__ void __launch_bounds__(NT) cell_kernel(Batch B)
+__global__ void __launch_bounds__(NT, (PPT2 > 0 ? 3 : 1)) cell_kernel(Batch B)
 {
     // one workgroup per cell (no loop over cells: a loop would let the
     // compiler hoist constants across the whole cell body)
