@@ -1422,8 +1422,13 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     return 0;
 }
 
+// Workgroups per CU asked of the register allocator: the kernel waits on
+// memory, LDS and barriers about half of its time, so more cells in flight
+// pay for some register spills: 4 for the 1-, 2- and 4-slot shapes (128
+// VGPRs), 3 for 4|6 (168 VGPRs); measured 9 % (C2 pair) to 32 % (cavity)
+// faster than without spills at 3 and 2 workgroups per CU.
 template <typename real, int DIM, int NT, int PPT, int PPT2, bool XB>
-__global__ void __launch_bounds__(NT, (PPT2 > 0 ? 3 : 1)) cell_kernel(Batch B)
+__global__ void __launch_bounds__(NT, (PPT2 > 0 ? 3 : (PPT <= 4 ? 4 : 1))) cell_kernel(Batch B)
 {
     // one workgroup per cell (no loop over cells: a loop would let the
     // compiler hoist constants across the whole cell body)
