@@ -1,0 +1,76 @@
+"""The paper's printed accuracy number, reproduced by the library: the
+reduced mass flow rate of the slit into vacuum at delta = 20 (Section 4.5,
+Eq. 40-41; tests/golden/slit_mass_flow.txt).
+
+The 400 x 200 half domain of the slit workload (chambers 10a wide and 10a
+high, cell a/20, dt = 0.3 dx / mean speed), upstream reservoir at n1 = 1e20
+m^-3 and 273 K, vacuum downstream.  delta = a p1 / (mu1 v1) relates to the
+Knudsen number of the builder (lambda of Eq. 36 over a) by Kn = 16 / (10
+sqrt(pi) delta).  The mass flow through the slit is, in the steady state,
+the flux through any vertical line next to the plate: the columns of cells
+on either side of x = 0 (the plate's faces carry no net flux), sum over y of
+rho u_x dy, doubled for the lower half; averaged over the last two thirds
+of 8000 steps.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1808_03801_amd import problems as P
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "slit_mass_flow.txt")
+
+
+def _golden():
+    rows = [l.split() for l in open(GOLDEN) if l.strip() and not l.startswith("#")]
+    return {float(d): float(w) for d, w in rows}
+
+
+def test_golden_fixture_and_delta_to_kn():
+    """CPU: the fixture parses, and delta = 20 maps to lambda / a = 0.0451
+    (Eq. 36 against Eq. 40: lambda = 16 / (10 sqrt(pi)) mu v1 / p)"""
+    assert _golden() == {20.0: 1.535}
+    gas = P.Gas(omega=0.5)
+    n1, T1 = 1.0e20, 273.0
+    p1 = n1 * gas.kB * T1
+    v1 = math.sqrt(2 * gas.kB * T1 / gas.m)
+    a = 20.0 * gas.mu(T1) * v1 / p1
+    lam = gas.mean_free_path(gas.m * n1, p1, T1)
+    assert abs(lam / a - 16.0 / (10.0 * math.sqrt(math.pi)) / 20.0) < 1e-12
+
+
+@pytest.mark.gpu
+def test_slit_reduced_mass_flow_rate_at_delta_20():
+    from paper_1808_03801_amd import usp
+    delta = 20.0
+    W_ref = _golden()[delta]
+    pb = P.slit_2d(Kn=16.0 / (10.0 * math.sqrt(math.pi)) / delta, p_ratio=math.inf, seed=7)
+    a, p1 = pb.meta["a"], pb.meta["p1"]
+    v1 = math.sqrt(2 * pb.gas.kB * 273.0 / pb.gas.m)
+    m_fm = a * p1 / (math.sqrt(math.pi) * v1)
+    half = pb.nx // 2
+    ctx = usp.Context(0)
+    try:
+        ctx.set_graph(True)
+        g = ctx.add(pb)
+        steps, acc = 8000, []
+        for k in range(steps // 10):
+            ctx.step([g], 10)
+            if (k + 1) % 50 == 0:
+                ctx.sync()
+                print("step", (k + 1) * 10, flush=True)
+            if (k + 1) * 10 > steps // 3:
+                f = g.fields(0).reshape(pb.ny, pb.nx, -1)
+                flux = f[:, :, 1] * f[:, :, 2]
+                acc.append(flux[:, half - 1:half + 1].sum(axis=0) * pb.dy)
+        assert g.status() == 0
+    finally:
+        ctx.close()
+    W = 2.0 * np.array(acc) / m_fm
+    b = W[: (len(W) // 10) * 10].reshape(10, -1, 2).mean(axis=1)
+    w, se = b.mean(), b.mean(axis=1).std() / math.sqrt(10)
+    print("W = %.4f +- %.4f (left column %.4f, right %.4f), reference %.3f"
+          % (w, se, b[:, 0].mean(), b[:, 1].mean(), W_ref))
+    assert abs(w / W_ref - 1.0) < 0.02
