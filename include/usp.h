@@ -201,6 +201,20 @@ usp_status usp_set_state(usp_ctx* ctx, int id, const int* counts, const double* 
  * S0, rho, u[3], T, p, sigma[6] (xx yy zz xy xz yz), q[3], P_ne, count. */
 usp_status usp_get_fields(usp_ctx* ctx, int id, int which, double* out);
 
+/* The same field record on the device, borrowed (no copy, no
+ * synchronisation): the fields are computed on the context's stream into a
+ * buffer of the instance, field-major: data[k * ncell + c] for field k of
+ * cell c, k as in usp_get_fields (nfield = 18).  The buffer belongs to the
+ * instance (allocated on first use, freed with it); its contents stay valid
+ * until the next usp_step, usp_set_state, usp_moments or usp_instance_free
+ * of the instance.  USP_EINVAL for a bad id, which or out; USP_ENOMEM when
+ * the buffer cannot be allocated. */
+typedef struct {
+    int ncell, nfield;
+    const double* data;
+} usp_moments_view;
+usp_status usp_moments(usp_ctx* ctx, int id, int which, usp_moments_view* out);
+
 /* Per-cell diagnostics, [ncell][48] (enable first with usp_set_diag; costs a
  * few record writes per cell per step).  Slots 0..31 describe the last step
  * (same meaning as the oracle's record); slots 32..46 accumulate the shader

@@ -173,7 +173,9 @@ __global__ void init_kernel(Batch B, const double* init_n, const double* init_u,
 }
 
 // field record per cell (usp_get_fields)
-__global__ void fields_out_kernel(Batch B, int which, double* out)
+// the field record of every cell: out[c][18] (cell-major) or, with
+// field_major, out[k][ncell]
+__global__ void fields_out_kernel(Batch B, int which, double* out, int field_major)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const InstDev& I = B.inst[0];
@@ -188,7 +190,7 @@ __global__ void fields_out_kernel(Batch B, int which, double* out)
     }
     CellF f;
     derive(I, m, which == 1 ? 2 : I.cnt[c], f);
-    double* r = out + (size_t)18 * c;
+    double r[18];
     for (int k = 0; k < 18; ++k) r[k] = 0.0;
     r[0] = m[0];
     r[1] = I.F * m[0];
@@ -201,6 +203,10 @@ __global__ void fields_out_kernel(Batch B, int which, double* out)
     }
     r[16] = I.pcur[c];
     r[17] = I.cnt[c];
+    for (int k = 0; k < 18; ++k) {
+        if (field_major) out[(size_t)k * I.ncell + c] = r[k];
+        else out[(size_t)18 * c + k] = r[k];
+    }
 }
 
 // device Philox for checking the generator

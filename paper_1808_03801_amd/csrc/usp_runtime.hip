@@ -30,7 +30,7 @@ __global__ void fields_kernel(Batch B, int init);
 __global__ void ctl_kernel(Batch B, int relaxed);
 __global__ void philox_kernel(const uint32_t* ctr, uint32_t k0, uint32_t k1, int n,
                               uint32_t* out);
-__global__ void fields_out_kernel(Batch B, int which, double* out);
+__global__ void fields_out_kernel(Batch B, int which, double* out, int field_major);
 }  // namespace usp
 
 using namespace usp;
@@ -46,6 +46,7 @@ struct Instance {
     bool alive = false;
     bool diag_on = false;
     int first = -1;       // first launch shape (-1: the default)
+    double* fview = nullptr;  // usp_moments buffer [18][ncell]
     int top() const { return pick_shape_index(h.max_ppc); }
     // open faces or the plate: the kernel variant with the extended boundary set
     int xb() const { return (h.open_mask != 0 || h.plate) ? 1 : 0; }
@@ -688,6 +689,7 @@ usp_status usp_instance_free(usp_ctx* ctx, int id)
     for (void* p : in->allocs) dfree(ctx, p, 0);
     ctx->allocated -= std::min(ctx->allocated, in->bytes);
     in->allocs.clear();
+    in->fview = nullptr;
     in->alive = false;
     drop_groups(ctx);
     return USP_OK;
@@ -1079,11 +1081,33 @@ usp_status usp_get_fields(usp_ctx* ctx, int id, int which, double* out)
     HIPCHK(ctx, hipMalloc(&d, ncell * 18 * 8));
     Batch B = single_batch(in, 0);
     hipLaunchKernelGGL(fields_out_kernel, dim3((ncell + 255) / 256), dim3(256), 0, ctx->stream, B,
-                       which, d);
+                       which, d, 0);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipMemcpyAsync(out, d, ncell * 18 * 8, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     (void)hipFree(d);
+    return USP_OK;
+}
+
+usp_status usp_moments(usp_ctx* ctx, int id, int which, usp_moments_view* out)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in || !out || (which != 0 && which != 1))
+        return fail(ctx, USP_EINVAL, "bad moments arguments");
+    const size_t ncell = (size_t)in->h.ncell;
+    if (!in->fview) {
+        in->fview = (double*)dalloc(ctx, ncell * 18 * 8);
+        if (!in->fview) return fail(ctx, USP_ENOMEM, "moments view");
+        in->allocs.push_back(in->fview);
+        in->bytes += ncell * 18 * 8;
+    }
+    Batch B = single_batch(in, 0);
+    hipLaunchKernelGGL(fields_out_kernel, dim3((ncell + 255) / 256), dim3(256), 0, ctx->stream, B,
+                       which, in->fview, 1);
+    HIPCHK(ctx, hipGetLastError());
+    out->ncell = (int)ncell;
+    out->nfield = 18;
+    out->data = in->fview;
     return USP_OK;
 }
 

@@ -348,7 +348,7 @@ def open_channel_1d(Kn=0.1, ncell=50, ppc=100, n_hi=1.0, T_lo=273.0, T_hi=273.0,
 
 def slit_2d(Kn=0.01, a_cells=20, ppc=100, p_ratio=2.0, T1=273.0, n1=1.0e20, omega=0.5,
             precision=32, seed=0, pne_mode=PNE_GLL_AVG, jmom_mode=JMOM_AVG,
-            spawn_projection=0, avg_init=1, n_avg=300, weight_mode=WEIGHT_LITERAL,
+            spawn_projection=0, avg_init=1, n_avg=300, weight_mode=WEIGHT_LITERAL, cfl=0.3,
             name="slit") -> Problem:
     """Flow through a slit of width a between two chambers (Section 4.5),
     half domain by the symmetry plane y = 0: x in [-10a, 10a], y in [0, 10a],
@@ -359,7 +359,7 @@ def slit_2d(Kn=0.01, a_cells=20, ppc=100, p_ratio=2.0, T1=273.0, n1=1.0e20, omeg
     right and on the top of the right chamber.  Kn = lambda_1 / a with the
     Eq. 36 mean free path of the upstream state; hard spheres by default (the
     paper's slit gas).  The chambers start at their reservoirs' states;
-    ppc is the mean over the domain; dt = 0.3 dx / mean speed (nu_ES dt =
+    ppc is the mean over the domain; dt = cfl dx / mean speed (cfl = 0.3: nu_ES dt =
     0.08 at Kn = 0.1 and 0.8 at Kn = 0.01).  Added-particle weights as Eq. 26
     prints them: with the consistent weights (1 / (nu_ES dt) larger) the
     conservation correction of those heavy particles heats the downstream
@@ -383,7 +383,7 @@ def slit_2d(Kn=0.01, a_cells=20, ppc=100, p_ratio=2.0, T1=273.0, n1=1.0e20, omeg
     return _sized(Problem(name=name, gas=gas, dim=2, nx=nx, ny=ny, x0=-10.0 * a, x1=10.0 * a,
                    y0=0.0, y1=10.0 * a, dx=d, dy=d, inv_dx=1.0 / d, inv_dy=1.0 / d,
                    vcell=d * d, faces=faces, accel=(0.0, 0.0, 0.0),
-                   dt=0.3 * d / gas.mean_speed(T1), Np=0.5 * (n1 + n2) * d * d / ppc,
+                   dt=cfl * d / gas.mean_speed(T1), Np=0.5 * (n1 + n2) * d * d / ppc,
                    init_n=n, init_u=np.zeros((nc, 3)), init_T=np.full(nc, T1),
                    precision=precision, seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
                    spawn_projection=spawn_projection, avg_init=avg_init, n_avg=n_avg,

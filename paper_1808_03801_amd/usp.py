@@ -60,6 +60,10 @@ ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
+class MomentsView(C.Structure):
+    _fields_ = [("ncell", C.c_int), ("nfield", C.c_int), ("data", C.c_void_p)]
+
+
 class Device(C.Structure):
     _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p),
                 ("stream", C.c_void_p), ("device", C.c_int), ("budget", C.c_size_t)]
@@ -105,6 +109,7 @@ def lib():
             "usp_get_shape": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                         C.POINTER(C.c_int)]),
             "usp_get_timing": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
+            "usp_moments": (C.c_int, [vp, C.c_int, C.c_int, C.POINTER(MomentsView)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -120,7 +125,22 @@ def exported_symbols():
             "usp_instance_free", "usp_step", "usp_sync", "usp_instance_status", "usp_num_cells",
             "usp_num_particles", "usp_get_state", "usp_set_state", "usp_get_fields",
             "usp_set_diag", "usp_get_diag", "usp_set_block", "usp_philox", "usp_set_timing",
-            "usp_get_timing", "usp_set_graph", "usp_set_shape", "usp_get_shape"]
+            "usp_get_timing", "usp_set_graph", "usp_set_shape", "usp_get_shape", "usp_moments"]
+
+
+_hiplib = None
+
+
+def _hip():
+    """the HIP runtime (already loaded by torch), for device-to-device copies
+    of borrowed library buffers"""
+    global _hiplib
+    if _hiplib is None:
+        _hiplib = C.CDLL("libamdhip64.so")
+        _hiplib.hipMemcpyAsync.restype = C.c_int
+        _hiplib.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int,
+                                           C.c_void_p]
+    return _hiplib
 
 
 def _dp(a):
@@ -325,6 +345,26 @@ class Instance:
     def fields(self, which: int = 0):
         out = np.zeros((self.ncell, NF))
         _check(self.ctx.h, lib().usp_get_fields(self.ctx.h, self.id, which, _dp(out)))
+        return out
+
+    def moments_view(self, which: int = 0):
+        """usp_moments: (ncell, nfield, device address of the field-major
+        [nfield][ncell] FP64 record), borrowed until the next step"""
+        v = MomentsView()
+        _check(self.ctx.h, lib().usp_moments(self.ctx.h, self.id, which, C.byref(v)))
+        return v.ncell, v.nfield, v.data
+
+    def moments_device(self, which: int = 0):
+        """the usp_moments record as a torch tensor [nfield][ncell] (a copy
+        on the device, made on the library's stream)"""
+        import torch
+        ncell, nfield, ptr = self.moments_view(which)
+        out = torch.empty((nfield, ncell), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        rc = _hip().hipMemcpyAsync(C.c_void_p(out.data_ptr()), C.c_void_p(ptr),
+                                   C.c_size_t(nfield * ncell * 8), 3,
+                                   C.c_void_p(self.ctx.stream.cuda_stream))
+        if rc != 0:
+            raise UspError(-5, f"hipMemcpyAsync failed ({rc})")
         return out
 
     def set_diag(self, on=True):

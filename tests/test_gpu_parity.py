@@ -363,3 +363,22 @@ def test_pass_timing():
         assert np.array_equal(sa.cells, sb.cells)
     finally:
         c.close()
+
+
+@pytest.mark.gpu
+def test_borrowed_device_moments_equal_the_host_fields(ctx):
+    """usp_moments (field-major, on the device, no copy) holds the same
+    numbers as usp_get_fields, for the instantaneous and the averaged fields"""
+    pb = _cases()["cavity_fp32"]()
+    g = ctx.add(pb)
+    try:
+        g.step(3)
+        for which in (0, 1):
+            ncell, nfield, ptr = g.moments_view(which)
+            assert (ncell, nfield) == (pb.ncell, 18) and ptr
+            dev = g.moments_device(which)
+            ctx.sync()
+            host = g.fields(which)
+            assert np.array_equal(dev.cpu().numpy().T, host)
+    finally:
+        g.free()
