@@ -57,6 +57,7 @@ enum { USP_WEIGHT_CONSISTENT = 0, USP_WEIGHT_LITERAL = 1 };
 enum { USP_CONSERVE_FULL = 0, USP_CONSERVE_NONE = 1 };
 enum { USP_JMOM_INST = 0, USP_JMOM_AVG = 1 };
 enum { USP_SCHEME_USP = 0, USP_SCHEME_SP = 1 };
+enum { USP_ES_SAMPLED = 0, USP_ES_MEAN = 1 };
 
 /* Gas (Section 4): Eq. 35 viscosity mu = mu_ref (T / T_ref)^omega; Pr of
  * Eq. 6 (nu_ES = Pr nu); molecular mass m and Boltzmann constant kB. */
@@ -125,7 +126,12 @@ typedef struct {
  * integer of N_c (1 - exp(-nu_ES dt)), the smallest rank keys of the cell)
  * reassigned and none deleted, their velocities a Maxwellian thermal
  * velocity mapped by Eq. 11 (S = I - (1 - Pr) / (2 Pr) sigma / p) around the
- * cell's velocity; the conservation correction as for USP. */
+ * cell's velocity; the conservation correction as for USP.
+ * es_mode: USP_ES_SAMPLED (the paper: each reassigned particle of step 6
+ * draws a time t from Eq. 29-30 and takes f_G with alpha(t) of Eq. 32) or
+ * USP_ES_MEAN: alpha replaced by its expectation over that time distribution,
+ * P + (1 - P) Pr (e^{(Pr - 1) nu dt} - 1) / ((Pr - 1)(e^{Pr nu dt} - 1)), one
+ * Gaussian per cell with the same second moments (Pr != 1 required). */
 typedef struct {
     double dt, Np, r_p, Kn_c, pne_fixed;
     int pne_mode, n_avg, avg_start, precision, weight_mode, conserve_mode, max_ppc;
@@ -133,6 +139,7 @@ typedef struct {
     uint64_t seed;
     int avg_init;
     int scheme;
+    int es_mode;
 } usp_numerics;
 
 /* Device binding.  alloc/free: device allocator (NULL = hipMalloc/hipFree);

@@ -44,6 +44,7 @@ class Config(C.Structure):
         ("face_Tb", C.c_double * 4),
         ("plate", C.c_int), ("plate_x", C.c_double), ("plate_ylo", C.c_double),
         ("plate_yhi", C.c_double), ("plate_T", C.c_double), ("scheme", C.c_int),
+        ("es_mode", C.c_int),
     ]
 
 
@@ -112,6 +113,7 @@ def make_config(pb) -> Config:
     g.plate, g.plate_x, g.plate_ylo, g.plate_yhi, g.plate_T = (pb.plate, pb.plate_x, pb.plate_ylo,
                                                               pb.plate_yhi, pb.plate_T)
     g.scheme = pb.scheme
+    g.es_mode = pb.es_mode
     for k in range(3):
         g.accel[k] = pb.accel[k]
     g.dt, g.Np, g.r_p, g.Kn_c, g.pne_fixed = pb.dt, pb.Np, pb.r_p, pb.Kn_c, pb.pne_fixed

@@ -868,8 +868,18 @@ static int resample(const uspo* o, const cellf* f, double pne, int cell, int slo
         resample_sp(o, f, cell, slot, q);
         return 0;
     }
-    double t = uspo_time_sample(ut, f->x, g->Pr * f->nu, g->dt);
-    double alpha = pne + (1.0 - pne) * exp(-f->nu * t);
+    double alpha;
+    if (g->es_mode == 1) {
+        /* the expectation of alpha(t) over the Eq. 29-30 time distribution,
+         * density nu_ES e^{nu_ES t} / (e^{nu_ES dt} - 1) on [0, dt]:
+         * E e^{-nu t} = Pr / (Pr - 1) (e^{(Pr - 1) nu dt} - 1) / (e^{Pr nu dt} - 1) */
+        double Pr = g->Pr, y = f->nu * g->dt;
+        double m = Pr / (Pr - 1.0) * expm1((Pr - 1.0) * y) / expm1(Pr * y);
+        alpha = pne + (1.0 - pne) * m;
+    } else {
+        double t = uspo_time_sample(ut, f->x, g->Pr * f->nu, g->dt);
+        alpha = pne + (1.0 - pne) * exp(-f->nu * t);
+    }
     double c = (1.0 - 1.0 / g->Pr) * alpha;
     double th = f->theta;
     double l00 = th * (1.0 + c * f->s[0]), l11 = th * (1.0 + c * f->s[1]);
@@ -1254,6 +1264,8 @@ static int check_config(const uspo_config* g)
         if (!(g->plate_ylo <= g->plate_yhi) || !(g->plate_T > 0.0)) return -1;
     }
     if (g->scheme != 0 && g->scheme != 1) return -1;
+    if (g->es_mode != 0 && g->es_mode != 1) return -1;
+    if (g->es_mode == 1 && !(g->Pr > 0.0 && g->Pr != 1.0)) return -1;
     /* SP-ESBGK has no added particles: P_ne fixed at 0 */
     if (g->scheme == 1 && !(g->pne_mode == 0 && g->pne_fixed == 0.0)) return -1;
     return 0;

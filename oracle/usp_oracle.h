@@ -63,6 +63,10 @@ typedef struct {
      * (P_ne fixed at 0), N_s of Eq. 9 particles reassigned, velocities from
      * the fixed target f_G of the cell through the linear map of Eq. 10-11 */
     int scheme;
+    /* f_G(t) of step 6: 0 = alpha(t) at a time drawn per particle from
+     * Eq. 29-30 (the paper); 1 = its expectation over that time
+     * distribution, one Gaussian per cell with the same second moments */
+    int es_mode;
 } uspo_config;
 
 /* per-cell state record: centred moments, raw sums, averaged raw sums of f^n,

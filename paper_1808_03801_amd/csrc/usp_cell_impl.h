@@ -430,6 +430,81 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
 // f_G(t) velocity of one reassigned particle (Table 2 step 6; Eq. 6c, 29-32).
 // The time-sample uniform is word 2 (rt) of the particle's selection draw.
 // ---------------------------------------------------------------------------
+// Cholesky factor of lambda = theta (I + (1 - 1/Pr) alpha sigma/p) (Eq. 6c
+// with the stress of Eq. 32), FP64; a pivot <= 1e-12 theta falls back to
+// theta I (fb = 1)
+struct EsFactor {
+    double L00, L10, L20, L11, L21, L22;
+    int fb;
+};
+
+__device__ __forceinline__ EsFactor es_factor(const InstDev& I, const CellF& f, double alpha)
+{
+    const double cc = (1.0 - 1.0 / I.Pr) * alpha;
+    const double th = f.theta;
+    const double l00 = th * (1.0 + cc * f.s[0]), l11 = th * (1.0 + cc * f.s[1]);
+    const double l22 = th * (1.0 + cc * f.s[2]);
+    const double l10 = th * cc * f.s[3], l20 = th * cc * f.s[4], l21 = th * cc * f.s[5];
+    const double tiny = 1e-12 * th;
+    EsFactor L;
+    L.L00 = L.L10 = L.L20 = L.L11 = L.L21 = L.L22 = 0.0;
+    L.fb = 0;
+    if (!(l00 > tiny)) L.fb = 1;
+    if (!L.fb) {
+        L.L00 = sqrt(l00);
+        const double iL00 = 1.0 / L.L00;
+        L.L10 = l10 * iL00;
+        L.L20 = l20 * iL00;
+        const double d1 = l11 - L.L10 * L.L10;
+        if (!(d1 > tiny)) L.fb = 1;
+        if (!L.fb) {
+            L.L11 = sqrt(d1);
+            L.L21 = (l21 - L.L20 * L.L10) / L.L11;
+            const double d2 = l22 - L.L20 * L.L20 - L.L21 * L.L21;
+            if (!(d2 > tiny)) L.fb = 1;
+            else L.L22 = sqrt(d2);
+        }
+    }
+    if (L.fb) {
+        L.L00 = L.L11 = L.L22 = sqrt(th);
+        L.L10 = L.L20 = L.L21 = 0.0;
+    }
+    return L;
+}
+
+// the velocity u + L z of one reassigned particle (Box-Muller z of its
+// RESAMPLE draw; single precision for FP32 state)
+template <typename real>
+__device__ __forceinline__ void es_draw(const InstDev& I, int cell, int slot, uint32_t step,
+                                        const CellF& f, const EsFactor& L, real& c0, real& c1,
+                                        real& c2)
+{
+    uint32_t r[4];
+    draw(I, step, PUR_RESAMPLE, 0u, (uint32_t)cell, (uint32_t)slot, r);
+    double z[3];
+    if (sizeof(real) == 4) {
+        float zf[3];
+        normal3_f(r, zf);
+        z[0] = zf[0];
+        z[1] = zf[1];
+        z[2] = zf[2];
+    } else {
+        normal3_d(r, I.prec, z);
+    }
+    c0 = (real)(f.U[0] + L.L00 * z[0]);
+    c1 = (real)(f.U[1] + L.L10 * z[0] + L.L11 * z[1]);
+    c2 = (real)(f.U[2] + L.L20 * z[0] + L.L21 * z[1] + L.L22 * z[2]);
+}
+
+// the expectation of alpha(t) (Eq. 32) over the Eq. 29-30 time distribution
+// (density nu_ES e^{nu_ES t} / (e^{nu_ES dt} - 1) on [0, dt])
+__device__ __forceinline__ double alpha_mean(const InstDev& I, const CellF& f, double pne)
+{
+    const double Pr = I.Pr, y = f.nu * I.dt;
+    const double m = Pr / (Pr - 1.0) * expm1((Pr - 1.0) * y) / expm1(Pr * y);
+    return pne + (1.0 - pne) * m;
+}
+
 template <typename real>
 __device__ __forceinline__ int resample_one(const InstDev& I, int cell, int slot, uint32_t step,
                                             const CellF& f, double pne, uint32_t rt, real& c0,
@@ -471,49 +546,9 @@ __device__ __forceinline__ int resample_one(const InstDev& I, int cell, int slot
         const double t = I.dt + log(u + (1.0 - u) * exp(-f.x)) / (I.Pr * f.nu);
         alpha = pne + (1.0 - pne) * exp(-f.nu * t);
     }
-    const double cc = (1.0 - 1.0 / I.Pr) * alpha;
-    const double th = f.theta;
-    const double l00 = th * (1.0 + cc * f.s[0]), l11 = th * (1.0 + cc * f.s[1]);
-    const double l22 = th * (1.0 + cc * f.s[2]);
-    const double l10 = th * cc * f.s[3], l20 = th * cc * f.s[4], l21 = th * cc * f.s[5];
-    const double tiny = 1e-12 * th;
-    double L00 = 0, L10 = 0, L20 = 0, L11 = 0, L21 = 0, L22 = 0;
-    int fb = 0;
-    if (!(l00 > tiny)) fb = 1;
-    if (!fb) {
-        L00 = sqrt(l00);
-        const double iL00 = 1.0 / L00;
-        L10 = l10 * iL00;
-        L20 = l20 * iL00;
-        const double d1 = l11 - L10 * L10;
-        if (!(d1 > tiny)) fb = 1;
-        if (!fb) {
-            L11 = sqrt(d1);
-            L21 = (l21 - L20 * L10) / L11;
-            const double d2 = l22 - L20 * L20 - L21 * L21;
-            if (!(d2 > tiny)) fb = 1;
-            else L22 = sqrt(d2);
-        }
-    }
-    if (fb) {
-        L00 = L11 = L22 = sqrt(th);
-        L10 = L20 = L21 = 0.0;
-    }
-    draw(I, step, PUR_RESAMPLE, 0u, (uint32_t)cell, (uint32_t)slot, r);
-    double z[3];
-    if (sizeof(real) == 4) {
-        float zf[3];
-        normal3_f(r, zf);
-        z[0] = zf[0];
-        z[1] = zf[1];
-        z[2] = zf[2];
-    } else {
-        normal3_d(r, I.prec, z);
-    }
-    c0 = (real)(f.U[0] + L00 * z[0]);
-    c1 = (real)(f.U[1] + L10 * z[0] + L11 * z[1]);
-    c2 = (real)(f.U[2] + L20 * z[0] + L21 * z[1] + L22 * z[2]);
-    return fb;
+    const EsFactor L = es_factor(I, f, alpha);
+    es_draw<real>(I, cell, slot, step, f, L, c0, c1, c2);
+    return L.fb;
 }
 
 // k-th smallest (1-based) rank key among the selected particles.  The keys
@@ -950,13 +985,25 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             mark(4);
             // step 6
             double fbs[1] = {0.0};
+            if (I.es_mode == 1 && !sp) {
+                // one Gaussian for the cell: alpha's expectation, one factor
+                const EsFactor Lc = es_factor(I, f, alpha_mean(I, f, Pn));
 #pragma unroll
-            for (int k = 0; k < PPT; ++k)
-                if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
-                    fbs[0] += (double)resample_one(I, c, k * NT + tid, step, f, Pn, rtime[k],
-                                                   P.c0[k], P.c1[k], P.c2[k]);
-                    P.w[k] = (real)1.0;
-                }
+                for (int k = 0; k < PPT; ++k)
+                    if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
+                        es_draw<real>(I, c, k * NT + tid, step, f, Lc, P.c0[k], P.c1[k], P.c2[k]);
+                        fbs[0] += (double)Lc.fb;
+                        P.w[k] = (real)1.0;
+                    }
+            } else {
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+                    if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
+                        fbs[0] += (double)resample_one(I, c, k * NT + tid, step, f, Pn, rtime[k],
+                                                       P.c0[k], P.c1[k], P.c2[k]);
+                        P.w[k] = (real)1.0;
+                    }
+            }
             mark(5);
             // step 7
             const int n7 = spawn_r<NT>(I, P, L, 7, c, ix, iy, step, f, Pn, nl, nl, tid, &errbits,

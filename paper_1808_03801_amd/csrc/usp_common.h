@@ -76,6 +76,7 @@ struct InstDev {
     int pne_mode, n_avg, avg_start, prec, weight_mode, conserve_mode, max_ppc, jmom_mode, proj;
     int avg_init;
     int scheme;  // 0 USP-ESBGK, 1 SP-ESBGK (Table 1)
+    int es_mode;  // 0 alpha(t) per particle (Eq. 29-32), 1 its expectation per cell
     uint32_t key0, key1;
     // sort window: source offsets -Kx..Kx, -Ky..Ky; nb = (2Ky+1)(2Kx+1) bins
     int Kx, Ky, nbx, nb;

@@ -209,6 +209,10 @@ usp_status validate(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb, con
         return fail(ctx, USP_EINVAL, "open faces cannot be combined with a body acceleration");
     if (nm->scheme != USP_SCHEME_USP && nm->scheme != USP_SCHEME_SP)
         return fail(ctx, USP_EINVAL, "unknown scheme");
+    if (nm->es_mode != USP_ES_SAMPLED && nm->es_mode != USP_ES_MEAN)
+        return fail(ctx, USP_EINVAL, "unknown es_mode");
+    if (nm->es_mode == USP_ES_MEAN && !(gas->Pr > 0.0 && gas->Pr != 1.0))
+        return fail(ctx, USP_EINVAL, "es_mode MEAN needs 0 < Pr != 1");
     if (nm->scheme == USP_SCHEME_SP && !(nm->pne_mode == USP_PNE_FIXED && nm->pne_fixed == 0.0))
         return fail(ctx, USP_EINVAL, "SP-ESBGK needs pne_mode FIXED with pne_fixed 0");
     if (pb->plate) {
@@ -547,6 +551,7 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
     h.proj = nm->spawn_projection;
     h.avg_init = nm->avg_init != 0;
     h.scheme = nm->scheme;
+    h.es_mode = nm->es_mode;
     h.key0 = (uint32_t)(nm->seed & 0xFFFFFFFFu);
     h.key1 = (uint32_t)(nm->seed >> 32);
     Window w = choose_window(gas, pb, nm, init_u, init_T);

@@ -49,6 +49,9 @@ JMOM_INST, JMOM_AVG = 0, 1
 
 # the per-step scheme: USP-ESBGK (Table 2) or the SP-ESBGK baseline (Table 1)
 SCHEME_USP, SCHEME_SP = 0, 1
+# f_G(t) of step 6: alpha at a per-particle time sample (Eq. 29-32), or its
+# expectation over the time distribution (one Gaussian per cell)
+ES_SAMPLED, ES_MEAN = 0, 1
 
 FACE_XLO, FACE_XHI, FACE_YLO, FACE_YHI = 0, 1, 2, 3
 
@@ -150,6 +153,7 @@ class Problem:
     plate_yhi: float = 0.0
     plate_T: float = 273.0
     scheme: int = SCHEME_USP
+    es_mode: int = ES_SAMPLED
     meta: dict = field(default_factory=dict)
 
     @property

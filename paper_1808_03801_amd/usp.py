@@ -53,7 +53,8 @@ class Numerics(C.Structure):
                [(n, C.c_int) for n in ("pne_mode", "n_avg", "avg_start", "precision",
                                        "weight_mode", "conserve_mode", "max_ppc", "jmom_mode",
                                        "spawn_projection", "window")] + \
-               [("seed", C.c_uint64), ("avg_init", C.c_int), ("scheme", C.c_int)]
+               [("seed", C.c_uint64), ("avg_init", C.c_int), ("scheme", C.c_int),
+                ("es_mode", C.c_int)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -179,6 +180,7 @@ def to_c(pb):
     nm.seed = int(pb.seed)
     nm.avg_init = int(pb.avg_init)
     nm.scheme = int(pb.scheme)
+    nm.es_mode = int(pb.es_mode)
     return gas, p, nm
 
 

@@ -84,6 +84,11 @@ def _cases():
         "empty_start_fp32": lambda: P.open_channel_1d(Kn=0.5, ncell=30, ppc=100, n_hi=0.0,
                                                       empty=True, precision=32, seed=29),
         "sod_fp32_8slot": lambda: P.sod_1d(ncell=40, mean_ppc=760, seed=28),
+        # step 6 with the mean ES target (alpha's expectation, one factor per cell)
+        "thermal_couette_esmean_fp32": lambda: P.thermal_couette_1d(
+            ncell=120, ppc=200, Kn=1e-2, seed=30).replace(es_mode=P.ES_MEAN),
+        "c1_esmean_fp64": lambda: P.couette_1d(ncell=40, ppc=100, seed=31).replace(
+            es_mode=P.ES_MEAN),
         # the SP-ESBGK baseline (Table 1)
         "c1_sp_fp64": lambda: P.sp_esbgk(P.couette_1d(ncell=40, ppc=100, seed=25)),
         "cavity_sp_fp32": lambda: P.sp_esbgk(P.cavity_2d(Kn=0.01, n=16, ppc=80, seed=26)),
