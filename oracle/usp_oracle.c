@@ -157,7 +157,7 @@ enum {
     D_CHOLFB, D_M0, D_P0X, D_P0Y, D_P0Z, D_E0, D_M1, D_P1X, D_P1Y, D_P1Z, D_E1, D_CLAMP,
     D_MARG_SEL, D_MARG_ROUND, D_MARG_CNT, D_WR, D_S2, D_MARG_CNT2, D_NINJ, D_NGONE
 };
-enum { F_SKIP = 1, F_FAILMASS = 2, F_FAILENERGY = 4, F_NOUSP = 8 };
+enum { F_SKIP = 1, F_FAILMASS = 2, F_FAILENERGY = 4, F_NOUSP = 8, F_WHOLE = 16 };
 
 struct uspo {
     uspo_config g;
@@ -941,6 +941,62 @@ static void use_averaged_sh(const uspo* o, const double* avg_raw, cellf* f)
     for (int k = 0; k < 3; ++k) f->h[k] = fa.valid ? fa.h[k] : 0.0;
 }
 
+/* Conservation where the reassigned particles alone cannot carry it (a
+ * common weight outside [1/2, 2], or a shift / scale outside its window):
+ * the reassigned particles take the common weight W_r that restores the
+ * cell's mass (any W_r > 0), and then every particle that stays in the cell
+ * (survivors, reassigned, step-7 particles) gets one shift and scale,
+ *   c -> P0 / M0 + s (c - u),   s^2 = (E0 - |P0|^2 / (2 M0)) / K,
+ * with u and K the mean velocity and thermal energy of that set, so that the
+ * cell's momentum and energy equal those of f-tilde^*.  Made where it is a
+ * correction: at least two reassigned particles (with one, the cell keeps
+ * the one-particle change), W_r > 0, K > 0, a shift of at most 3 rms
+ * thermal speeds and s^2 in [1/4, 4] (a wider scale, with K a difference of
+ * the positive- and negative-weight particles' energies, can spread a cell's
+ * velocities far enough to destabilise it at a few dozen particles per
+ * cell).  Returns 1
+ * if made, 0 (nothing changed) otherwise.  Mr, Pr, Er: mass, momentum and
+ * energy of the survivors and the step-7 particles. */
+static int whole_cell(const uspo* o, plist* L, const selinfo* si, int nl, plist* L7, int nusp,
+                      double M0, const double P0[3], double E0, double Mr, const double Pr[3],
+                      double Er)
+{
+    const uspo_config* g = &o->g;
+    double Wr = (M0 - Mr) / nusp;
+    double sc[3] = {0, 0, 0}, sq = 0.0;
+    for (int i = 0; i < nl; ++i)
+        if (si[i].fate == 1)
+            for (int k = 0; k < 3; ++k) {
+                sc[k] += L->p[i].c[k];
+                sq += L->p[i].c[k] * L->p[i].c[k];
+            }
+    int ok = nusp >= 2 && Wr > 0.0;
+    double M = Mr + Wr * nusp, u[3], a[3], u2 = 0.0, a2 = 0.0, du2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        u[k] = (Pr[k] + Wr * sc[k]) / M;
+        a[k] = P0[k] / M0;
+        u2 += u[k] * u[k];
+        a2 += a[k] * a[k];
+        du2 += (a[k] - u[k]) * (a[k] - u[k]);
+    }
+    double K = Er + 0.5 * Wr * sq - 0.5 * M * u2;
+    double s2 = (E0 - 0.5 * M0 * a2) / K;
+    ok = ok && M > 0.0 && K > 0.0 && du2 <= 9.0 * 2.0 * K / M && s2 >= 0.25 && s2 <= 4.0;
+    if (!ok) return 0;
+    double s = sqrt(s2);
+    for (int pass = 0; pass < 2; ++pass) {
+        part* pp = pass == 0 ? L->p : L7->p;
+        int np = pass == 0 ? nl : L7->n;
+        for (int i = 0; i < np; ++i) {
+            if (pass == 0 && si[i].fate == 2) continue;
+            part* q = &pp[i];
+            if (pass == 0 && si[i].fate == 1) q->w = st(g, Wr);
+            for (int k = 0; k < 3; ++k) q->c[k] = st(g, a[k] + s * (q->c[k] - u[k]));
+        }
+    }
+    return 1;
+}
+
 static void relax_cell(uspo* o, int d, plist* L, double* dg)
 {
     const uspo_config* g = &o->g;
@@ -1096,15 +1152,23 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
                     } else {
                         flags |= F_FAILENERGY;
                     }
-                    for (int i = 0; i < nl; ++i)
-                        if (si[i].fate == 1) {
-                            part* q = &L->p[i];
-                            if (shift)
-                                for (int k = 0; k < 3; ++k)
-                                    q->c[k] = st(g, a[k] + s * (q->c[k] - cb[k]));
-                            q->w = st(g, Wr);
-                        }
+                    int whole = (flags & F_FAILENERGY) &&
+                                whole_cell(o, L, si, nl, &L7, nusp, M0, P0, E0, Mr, Pr_, Er);
+                    if (whole)
+                        flags = (flags & ~F_FAILENERGY) | F_WHOLE;
+                    else
+                        for (int i = 0; i < nl; ++i)
+                            if (si[i].fate == 1) {
+                                part* q = &L->p[i];
+                                if (shift)
+                                    for (int k = 0; k < 3; ++k)
+                                        q->c[k] = st(g, a[k] + s * (q->c[k] - cb[k]));
+                                q->w = st(g, Wr);
+                            }
                 }
+                if ((flags & F_FAILMASS) &&
+                    whole_cell(o, L, si, nl, &L7, nusp, M0, P0, E0, Mr, Pr_, Er))
+                    flags = (flags & ~F_FAILMASS) | F_WHOLE;
             }
         }
 

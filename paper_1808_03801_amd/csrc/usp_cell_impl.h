@@ -1047,11 +1047,12 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                     WrOut = Wr;
                     // a correction only where it is one: common weight in
                     // [1/2, 2], mean shift within 3 rms spreads, scale in [1/3, 3]
+                    double a[3], cb[3], sc = 1.0;
+                    bool shift = true;
                     if (!(Wr >= 0.5 && Wr <= 2.0)) {
                         flags |= F_FAILMASS;
                     } else {
                         const double MR = Wr * nusp;
-                        double a[3], cb[3];
 #pragma unroll
                         for (int q = 0; q < 3; ++q) {
                             a[q] = (Ms[27 + q] - cs[1 + q]) / MR;
@@ -1065,8 +1066,6 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                         double da2 = 0.0;
 #pragma unroll
                         for (int q = 0; q < 3; ++q) da2 += (a[q] - cb[q]) * (a[q] - cb[q]);
-                        double sc = 1.0;
-                        bool shift = true;
                         if (nusp >= 2 && D > 0.0) {
                             if (!(da2 <= 9.0 * D / nusp)) {
                                 // the mean would move by more than 3 rms spreads
@@ -1082,6 +1081,47 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                         } else {
                             flags |= F_FAILENERGY;
                         }
+                    }
+                    // where the reassigned particles alone cannot carry it:
+                    // W_r on them (mass), then one shift and scale of every
+                    // particle that stays in the cell (momentum, energy), with
+                    // at least two reassigned, W_r > 0, a positive thermal
+                    // energy K of the set, a shift within 3 rms thermal speeds
+                    // and a scale^2 in [1/4, 4]
+                    bool whole = false;
+                    double aw[3], uw[3], sw = 1.0;
+                    if (nusp >= 2 && (flags & (F_FAILMASS | F_FAILENERGY))) {
+                        const double M = cs[0] + Wr * nusp;
+                        double u2 = 0.0, a2 = 0.0, du2 = 0.0;
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            uw[q] = (cs[1 + q] + Wr * cs[5 + q]) / M;
+                            aw[q] = Ms[27 + q] / M0;
+                            u2 += uw[q] * uw[q];
+                            a2 += aw[q] * aw[q];
+                            du2 += (aw[q] - uw[q]) * (aw[q] - uw[q]);
+                        }
+                        const double K = cs[4] + 0.5 * Wr * cs[8] - 0.5 * M * u2;
+                        const double s2 = (Ms[26] - 0.5 * M0 * a2) / K;
+                        whole = Wr > 0.0 && M > 0.0 && K > 0.0 && du2 <= 9.0 * 2.0 * K / M &&
+                                s2 >= 0.25 && s2 <= 4.0;
+                        if (whole) {
+                            sw = sqrt(s2);
+                            flags = (flags & ~(F_FAILMASS | F_FAILENERGY)) | F_WHOLE;
+                        }
+                    }
+                    if (whole) {
+#pragma unroll
+                        for (int k = 0; k < PPT; ++k) {
+                            if (k * NT >= npu) continue;
+                            const int fk = fate(P, k);
+                            if (fk != FT_KEEP && fk != FT_REASSIGN) continue;
+                            if (fk == FT_REASSIGN) P.w[k] = (real)Wr;
+                            P.c0[k] = (real)(aw[0] + sw * ((double)P.c0[k] - uw[0]));
+                            P.c1[k] = (real)(aw[1] + sw * ((double)P.c1[k] - uw[1]));
+                            P.c2[k] = (real)(aw[2] + sw * ((double)P.c2[k] - uw[2]));
+                        }
+                    } else if (!(flags & F_FAILMASS)) {
 #pragma unroll
                         for (int k = 0; k < PPT; ++k)
                             if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
