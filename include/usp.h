@@ -112,7 +112,8 @@ typedef struct {
  * (0.1); pne_mode: USP_PNE_*, pne_fixed used by USP_PNE_FIXED; n_avg: Eq. 34
  * window (1000) and avg_start: first averaged step; precision: 32 or 64
  * (particle state); max_ppc: largest number of particles a cell may hold
- * during a step (<= 2048); jmom_mode: moments that build the added particles
+ * during a step (<= 2048; <= 1365 for a problem with open faces or the
+ * plate, else usp_create fails with USP_EINVAL); jmom_mode: moments that build the added particles
  * and the ES target (instantaneous Eq. 1 or averaged Eq. 34);
  * spawn_projection: 1 = project each added batch onto zero mass, momentum and
  * energy; window: sort-window half width in cells (0 = derive from the

@@ -493,7 +493,9 @@ static int spawn(const uspo* o, int batch, int cell, const cellf* f, double pne,
     const uspo_config* g = &o->g;
     if (!f->valid || !(pne > 0.0) || !(f->x > 0.0)) return 0;
     double m1 = f->x < 1.0 ? f->x : 1.0;
-    double v = f->S0 * m1 / g->r_p;
+    /* Eq. 25; held in [0, 1e6] (beyond every capacity) so that a blown-up
+     * cell ends in the capacity error instead of an int overflow */
+    double v = fmin(fmax(f->S0 * m1 / g->r_p, 0.0), 1.0e6);
     uint32_t r[4];
     draw(g, (uint32_t)o->step, PUR_SPAWN_CNT, (uint32_t)batch, (uint32_t)cell, 0, r);
     double u = uspo_uniform(r[0], g->precision);

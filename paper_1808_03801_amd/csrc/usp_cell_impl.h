@@ -270,7 +270,10 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
 {
     if (!f.valid || !(pne > 0.0) || !(f.x > 0.0)) return 0;
     const double m1 = f.x < 1.0 ? f.x : 1.0;
-    const double v = f.S0 * m1 / I.r_p;
+    // Eq. 25 count, held in [0, 1e6] before it becomes an int: a blown-up
+    // cell's S0 must reach the capacity test below, not overflow the int
+    // (a count of 2^31 wraps the capacity sums negative)
+    const double v = fmin(fmax(f.S0 * m1 / I.r_p, 0.0), 1.0e6);
     uint32_t r[4];
     draw(I, step, PUR_SPAWN_CNT, (uint32_t)batch, (uint32_t)cell, 0u, r);
     const double u = uni_d(r[0], I.prec);
@@ -697,9 +700,14 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     const bool can_defer = retry_local || tier_out != nullptr;
     auto defer = [&](int code) -> int {
         if (!retry_local && tid == 0) {
-            const int k = atomicAdd(&tier_out[0], 1);
-            if (k < tier_len) tier_out[1 + k] = g;
-            else atomicOr(&I.ctl[CTL_ERR], (int)ERR_CAPACITY);  // lists not cleared
+            if (!tier_out) {
+                // the last shape has nowhere to hand the cell: poison the instance
+                atomicOr(&I.ctl[CTL_ERR], (int)ERR_CAPACITY);
+            } else {
+                const int k = atomicAdd(&tier_out[0], 1);
+                if (k < tier_len) tier_out[1 + k] = g;
+                else atomicOr(&I.ctl[CTL_ERR], (int)ERR_CAPACITY);  // lists not cleared
+            }
         }
         return code;
     };

@@ -205,6 +205,12 @@ usp_status validate(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb, con
     if ((pb->face[0].kind == USP_BC_PERIODIC) != (pb->face[1].kind == USP_BC_PERIODIC) ||
         (pb->face[2].kind == USP_BC_PERIODIC) != (pb->face[3].kind == USP_BC_PERIODIC))
         return fail(ctx, USP_EINVAL, "a periodic face needs a periodic opposite face");
+    // the open-face / plate kernel variant runs in the shapes up to 256 x
+    // (4 | 6) slots: its 8-slot shape is switched off (a run of it faulted
+    // on the device with the cause not found)
+    if ((open || pb->plate) && pick_shape_index(nm->max_ppc) == NSHAPE - 1)
+        return fail(ctx, USP_EINVAL,
+                    "open faces or the plate: max_ppc must be at most 1365 (8-slot shape off)");
     if (open && (pb->accel[0] != 0.0 || pb->accel[1] != 0.0 || pb->accel[2] != 0.0))
         return fail(ctx, USP_EINVAL, "open faces cannot be combined with a body acceleration");
     if (nm->scheme != USP_SCHEME_USP && nm->scheme != USP_SCHEME_SP)

@@ -166,14 +166,22 @@ class Problem:
     def expected_particles(self) -> int:
         return int(np.sum(np.floor(self.init_n * self.vcell / self.Np + 0.5)))
 
+    def cap_limit(self) -> int:
+        """largest max_ppc the GPU library takes for this problem: 2048, or
+        1344 with open faces or the plate (that kernel variant stops at the
+        256 x (4 | 6) shape)"""
+        xb = self.plate or any(f.kind == BC_OPEN for f in self.faces)
+        return 1344 if xb else 2048
+
     def _capacity_for(self, ppc: int, factor: float = 3.0) -> "Problem":
-        cap = int(min(2048, max(64, -(-int(factor * ppc) // 64) * 64)))
+        cap = int(min(self.cap_limit(), max(64, -(-int(factor * ppc) // 64) * 64)))
         return self.replace(max_ppc=cap)
 
     def with_capacity(self, factor: float = 3.0) -> "Problem":
-        """max_ppc = factor x the fullest initial cell (multiple of 64, <= 2048)"""
+        """max_ppc = factor x the fullest initial cell (multiple of 64, at
+        most cap_limit())"""
         full = float(np.max(np.floor(self.init_n * self.vcell / self.Np + 0.5)))
-        cap = int(min(2048, max(64, -(-int(factor * full) // 64) * 64)))
+        cap = int(min(self.cap_limit(), max(64, -(-int(factor * full) // 64) * 64)))
         return self.replace(max_ppc=cap)
 
 
@@ -284,6 +292,37 @@ def sod_1d(Kn=1e-3, L=1.0, ncell=1000, mean_ppc=500, rho_ratio=8.0, p_ratio=10.0
                    seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
                    spawn_projection=spawn_projection,
                    meta=dict(L=L, lam_l=lam_l, tau_l=tau_l, rho_l=rho_l, p_l=p_l, T_r=T_r, Kn=Kn)))
+
+
+# Table 4: (rho_l in kg/m^3, [(N_cell, dt / tau_c,l), ...]) of the two Sod cases;
+# rho_r = rho_l / 8 and the two initial temperatures of Section 4.3
+SOD_TABLE4 = {1: (1e-5, [(400, 0.2), (100, 0.8), (50, 1.5)]),
+              2: (1e-4, [(1200, 0.2), (240, 1.0), (60, 4.0)])}
+SOD_T_L, SOD_T_R = 273.008012, 273.00641
+SOD_T_FINAL = 6.8e-4
+
+
+def sod_table4(case, row, mean_ppc=500, omega=0.81, precision=32, seed=0, open_ends=True,
+               **kw) -> Problem:
+    """One row of the paper's Sod series (Section 4.3, Table 4): tube of 1 m,
+    rho_l of the case, rho_r = rho_l / 8, the given T_l and T_r (pressure
+    ratio 8.00005), N_cell cells and dt = (dt / tau_c,l) tau_c,l with tau_c,l
+    of Eq. 37 at the left state; open ends.  The paper's 2e5 / 2.5e4
+    particles per cell (left / right) are replaced by mean_ppc (left
+    2 * 8/9 mean_ppc, right 2/9 of it); meta t_final = 6.8e-4 s and the
+    number of steps that reaches it."""
+    rho_l, rows = SOD_TABLE4[case]
+    ncell, dto = rows[row]
+    gas = Gas(omega=omega)
+    p_l = rho_l * gas.R * SOD_T_L
+    kn = gas.mean_free_path(rho_l, p_l, SOD_T_L)  # lambda_l / L with L = 1 m
+    pb = sod_1d(Kn=kn, ncell=ncell, mean_ppc=mean_ppc, rho_ratio=8.0,
+                p_ratio=8.0 * SOD_T_L / SOD_T_R, T_l=SOD_T_L, dt_over_tau=dto, omega=omega,
+                precision=precision, seed=seed, open_ends=open_ends,
+                name="sod_t4_%d_%d" % (case, row), **kw)
+    steps = int(round(SOD_T_FINAL / pb.dt))
+    meta = dict(pb.meta, case=case, row=row, t_final=SOD_T_FINAL, steps=steps)
+    return pb.replace(meta=meta)
 
 
 def poiseuille_1d(Kn=1e-3, dpdx=4.0e6, T_w=273.0, ncell=100, ppc=500, dt_over_tau=5.0,
