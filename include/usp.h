@@ -225,7 +225,10 @@ usp_status usp_moments(usp_ctx* ctx, int id, int which, usp_moments_view* out);
 
 /* Per-cell diagnostics, [ncell][48] (enable first with usp_set_diag; costs a
  * few record writes per cell per step).  Slots 0..31 describe the last step
- * (same meaning as the oracle's record); slots 32..46 accumulate the shader
+ * (same meaning as the oracle's record; slot 10 is a bit set: 1 invalid
+ * moments, no relaxation; 2 mass correction failed; 4 momentum / energy
+ * correction failed; 8 nothing reassigned; 16 whole-cell correction made);
+ * slots 32..46 accumulate the shader
  * cycles spent in each phase of the cell kernel (gather, moments, step 4,
  * selection, rank selection, resampling, step 7, conservation, compaction,
  * step-8 moments, step 2, advection, bin counts, bin offsets, writes). */

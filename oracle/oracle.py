@@ -18,6 +18,10 @@ NCS = 4 * NMOM + 2
 NF = 18
 NDIAG = 32
 
+# per-cell record of the last step; "flags" is a bit set: 1 the cell's
+# moments were invalid (no relaxation), 2 the mass correction failed, 4 the
+# momentum / energy correction failed, 8 nothing was reassigned, 16 the
+# whole-cell correction restored mass, momentum and energy
 DIAG = dict(n_in=0, n4=1, n_sel=2, n_usp=3, n_del=4, n7=5, n_out=6, n2=7, s_sel=8, p_sel=9,
             flags=10, chol_fb=11, M0=12, P0x=13, P0y=14, P0z=15, E0=16, M1=17, P1x=18, P1y=19,
             P1z=20, E1=21, clamp=22, marg_sel=23, marg_round=24, marg_cnt=25, Wr=26, s2=27,
