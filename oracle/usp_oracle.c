@@ -24,9 +24,12 @@
  *           the ES operator make those totals the right targets).  A
  *           correction is only made where it is one: a common weight in
  *           [1/2, 2], a shift of the mean of at most 3 rms spreads of the
- *           reassigned velocities, a scale in [1/3, 3]; otherwise that part is
- *           skipped and counted (with a few particles per cell, a tiny common
- *           weight would otherwise demand enormous velocities);
+ *           reassigned velocities, a scale in [1/3, 3]; otherwise (with a few
+ *           particles per cell, a tiny common weight would demand enormous
+ *           velocities) the whole cell is corrected instead: the reassigned
+ *           particles take the mass-restoring weight and every particle of
+ *           the cell one shift and scale (whole_cell), and where even that is
+ *           out of its window the failing part is skipped and counted;
  *   step 8  moments of f^{n+1} (Eq. 1), exponential time averaging (Eq. 34)
  *           and P_ne for the next step (Eq. 16-18 with lambda of Eq. 36).
  *
