@@ -79,6 +79,16 @@ def sp_kappa(dto):
     return y * math.exp(-y) / -math.expm1(-y)
 
 
+def sp_scheme_mu(dto):
+    """the SP-ESBGK scheme of Table 1 (Eq. 9-11): a fraction f = 1 - e^{-Pr x}
+    of the particles reassigned through the linear map takes the stress to
+    R sigma, R = 1 - f / Pr, so mu_eff / mu = x R / (1 - R); its heat flux
+    goes to (1 - f) q, the same as the P_ne = 0 limit's"""
+    x = NU_TAU * dto
+    R = 1.0 + 1.5 * math.expm1(-2.0 / 3.0 * x)
+    return x * R / (1.0 - R)
+
+
 def test_closed_forms():
     # the SP-ESBGK limit tends to the continuum value as dt -> 0 and falls
     # off with dt; heat flux relaxes more slowly (Pr < 1), so it lags less
@@ -111,10 +121,17 @@ def _run(builders, steps=3300, warm=500, every=4):
 
 @pytest.mark.gpu
 def test_gpu_viscosity_and_conductivity_against_the_time_step():
+    # pne -1: the SP-ESBGK scheme (its linear map over-relaxes the stress
+    # beyond dt ~ 1.5 tau_c, so only the smaller steps)
     cases = [(kind, dto, pne, seed) for kind in ("mu", "kappa") for dto in DTOS
-             for pne in (1.0, 0.0) for seed in (1, 2)]
-    builders = [(lambda k=k, d=d, p=p, s=s: (couette if k == "mu" else thermal)(d, p, s))
-                for k, d, p, s in cases]
+             for pne in (1.0, 0.0, -1.0) for seed in (1, 2)
+             if pne != -1.0 or dto <= 1.0]
+
+    def build(k, d, p, s):
+        pb = (couette if k == "mu" else thermal)(d, max(p, 0.0), s)
+        return P.sp_esbgk(pb) if p < 0 else pb
+
+    builders = [(lambda k=k, d=d, p=p, s=s: build(k, d, p, s)) for k, d, p, s in cases]
     pbs, fs = _run(builders)
     res = {}
     for (kind, dto, pne, seed), pb, f in zip(cases, pbs, fs):
@@ -122,7 +139,12 @@ def test_gpu_viscosity_and_conductivity_against_the_time_step():
         res.setdefault((kind, dto, pne), []).append(v)
     for (kind, dto, pne), v in sorted(res.items()):
         r = float(np.mean(v))
-        ref = 1.0 if pne == 1.0 else (sp_mu(dto) if kind == "mu" else sp_kappa(dto))
+        if pne == 1.0:
+            ref = 1.0
+        elif kind == "kappa":
+            ref = sp_kappa(dto)
+        else:
+            ref = sp_mu(dto) if pne == 0.0 else sp_scheme_mu(dto)
         print(kind, dto, pne, round(r, 4), "closed form", round(ref, 4))
         if pne == 1.0:
             assert abs(r - 1.0) < 0.06, (kind, dto, r)
