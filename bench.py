@@ -10,7 +10,8 @@ A "step" is one full time step (Table 2 steps 2-8) of both instances.
 value = live particles (weighted included) x steps / wall time of the timed
 region, with all state resident in HBM.
 
-Prints one JSON line (see the "roofline" and "cpu_baseline" members).
+Prints one JSON line (see the "roofline", "valu_issue" and "cpu_baseline"
+members).
 """
 import argparse
 import hashlib
@@ -50,17 +51,32 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per step from the committed rocprofv3 summary, or None when
+def _profile_figure(key):
+    """a per-step figure from the committed rocprofv3 summary, or None when
     it was taken on other kernel sources"""
     try:
         txt = open(PROFILE).read()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_step:\s*([0-9.eE+]+)\s+sources:\s*([0-9a-f]+)", txt)
+    m = re.search(key + r":\s*([0-9.eE+]+)\s+sources:\s*([0-9a-f]+)", txt)
     if not m or m.group(2) != kernel_source_hash():
         return None
     return float(m.group(1))
+
+
+def measured_traffic():
+    """HBM bytes per step (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"""
+    return _profile_figure("traffic_bytes_per_step")
+
+
+def measured_valu():
+    """VALU wave instructions per step (SQ_INSTS_VALU over the step's dispatches)"""
+    return _profile_figure("valu_instr_per_step")
+
+
+# wave64 VALU instructions the chip can issue per second: 256 CUs x 4 SIMDs,
+# one wave64 instruction per SIMD every 4 cycles (16 lanes), 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def copy_calibration():
@@ -251,6 +267,16 @@ def main():
             "avg_step_gpu_ms": step_ms,
             "bytes_per_step": bytes_per_step,
         },
+    }
+    # the same step seen from the vector ALUs: the kernel is bound by the
+    # latency of its per-cell phases, and this says how busy the VALUs are
+    valu = measured_valu()
+    line["valu_issue"] = None if valu is None else {
+        "instr_per_step": valu,
+        "achieved": valu / (step_ms * 1e-3),
+        "peak": VALU_ISSUE_PEAK,
+        "unit": "wave64 VALU instructions/s",
+        "frac": valu / (step_ms * 1e-3) / VALU_ISSUE_PEAK,
     }
     for i in inst:
         i.free()
