@@ -302,15 +302,18 @@ SOD_T_L, SOD_T_R = 273.008012, 273.00641
 SOD_T_FINAL = 6.8e-4
 
 
-def sod_table4(case, row, mean_ppc=500, omega=0.81, precision=32, seed=0, open_ends=True,
+def sod_table4(case, row, mean_ppc=500, omega=0.81, precision=32, seed=0, open_ends=False,
                **kw) -> Problem:
     """One row of the paper's Sod series (Section 4.3, Table 4): tube of 1 m,
     rho_l of the case, rho_r = rho_l / 8, the given T_l and T_r (pressure
     ratio 8.00005), N_cell cells and dt = (dt / tau_c,l) tau_c,l with tau_c,l
-    of Eq. 37 at the left state; open ends.  The paper's 2e5 / 2.5e4
-    particles per cell (left / right) are replaced by mean_ppc (left
-    2 * 8/9 mean_ppc, right 2/9 of it); meta t_final = 6.8e-4 s and the
-    number of steps that reaches it."""
+    of Eq. 37 at the left state.  Specular ends by default (no wave reaches
+    an end before t_final); open_ends gives the paper's open boundaries, for
+    which the GPU library holds at most 1365 particles per cell (at 500 per
+    cell the dense side outgrows that: take mean_ppc of about 350 there).
+    The paper's 2e5 / 2.5e4 particles per cell (left / right) are replaced by
+    mean_ppc (left 2 * 8/9 mean_ppc, right 2/9 of it); meta t_final =
+    6.8e-4 s and the number of steps that reaches it."""
     rho_l, rows = SOD_TABLE4[case]
     ncell, dto = rows[row]
     gas = Gas(omega=omega)
