@@ -266,7 +266,7 @@ def test_open_faces_refuse_the_8_slot_shape():
     """an instance with open faces whose max_ppc would need the 8-slot shape
     is refused before anything runs; at 1344 it is taken"""
     from paper_1808_03801_amd import usp
-    pb = P.sod_table4(2, 2, mean_ppc=300, seed=1)
+    pb = P.sod_table4(2, 2, mean_ppc=300, seed=1, open_ends=True)
     ctx = usp.Context(0)
     try:
         with pytest.raises(usp.UspError):
