@@ -161,3 +161,29 @@ def test_gpu_viscosity_and_conductivity_against_the_time_step():
             assert abs(r - 1.0) < 0.06, (kind, dto, r)
         else:
             assert abs(r - ref) < max(0.08 * ref, 0.03), (kind, dto, r, ref)
+
+
+@pytest.mark.gpu
+def test_gpu_viscosity_with_the_gll_switch_in_the_continuum():
+    """the paper's own P_ne (Eq. 16-18, from the time-averaged fields): at
+    Kn = 0.005 the GLL Knudsen number of the core is small, P_ne is close to
+    1, and the viscosity stays at mu for dt up to 5 tau_c"""
+    def build(dto, seed):
+        U, kn, ncell = 100.0, 0.005, 40
+        pb = P.couette_1d(Kn=kn, U_w=U, ncell=ncell, ppc=PPC, dt_over_tau=dto, omega=0.81,
+                          precision=32, seed=seed)
+        H, lam = pb.meta["H"], pb.meta["lam0"]
+        y = (np.arange(ncell) + 0.5) * H / ncell
+        iu = np.zeros((ncell, 3))
+        iu[:, 0] = U * (2.0 * y - H) / (H + 2.2 * lam)
+        return pb.replace(init_u=iu, n_avg=100)
+
+    cases = [(dto, seed) for dto in (1.0, 5.0) for seed in (1, 2)]
+    pbs, fs = _run([(lambda d=d, s=s: build(d, s)) for d, s in cases])
+    for dto in (1.0, 5.0):
+        v = [mu_eff(pb, f) for (d, _), pb, f in zip(cases, pbs, fs) if d == dto]
+        pne = np.mean([f[pb.ncell // 5: -pb.ncell // 5, 16].mean()
+                       for (d, _), pb, f in zip(cases, pbs, fs) if d == dto])
+        r = float(np.mean(v))
+        print("gll dt/tau", dto, "mu_eff", round(r, 4), "P_ne core", round(float(pne), 3))
+        assert abs(r - 1.0) < 0.06, (dto, r)
