@@ -58,6 +58,7 @@ enum { USP_CONSERVE_FULL = 0, USP_CONSERVE_NONE = 1 };
 enum { USP_JMOM_INST = 0, USP_JMOM_AVG = 1 };
 enum { USP_SCHEME_USP = 0, USP_SCHEME_SP = 1 };
 enum { USP_ES_SAMPLED = 0, USP_ES_MEAN = 1 };
+enum { USP_GLL_U_SOUND = 0, USP_GLL_U_LITERAL = 1 };
 
 /* Gas (Section 4): Eq. 35 viscosity mu = mu_ref (T / T_ref)^omega; Pr of
  * Eq. 6 (nu_ES = Pr nu); molecular mass m and Boltzmann constant kB. */
@@ -132,7 +133,11 @@ typedef struct {
  * draws a time t from Eq. 29-30 and takes f_G with alpha(t) of Eq. 32) or
  * USP_ES_MEAN: alpha replaced by its expectation over that time distribution,
  * P + (1 - P) Pr (e^{(Pr - 1) nu dt} - 1) / ((Pr - 1)(e^{Pr nu dt} - 1)), one
- * Gaussian per cell with the same second moments (Pr != 1 required). */
+ * Gaussian per cell with the same second moments (Pr != 1 required).
+ * gll_u: the velocity term of Eq. 18, lambda |grad |u|| / Q: USP_GLL_U_SOUND
+ * (Q = max(|u|, sqrt(5 theta / 3)), the convention of the GLL criterion's
+ * authors; finite at stagnation) or USP_GLL_U_LITERAL (Q = |u| as printed;
+ * a cell at rest with a velocity gradient gets P_ne = 0). */
 typedef struct {
     double dt, Np, r_p, Kn_c, pne_fixed;
     int pne_mode, n_avg, avg_start, precision, weight_mode, conserve_mode, max_ppc;
@@ -141,6 +146,7 @@ typedef struct {
     int avg_init;
     int scheme;
     int es_mode;
+    int gll_u;
 } usp_numerics;
 
 /* Device binding.  alloc/free: device allocator (NULL = hipMalloc/hipFree);

@@ -1270,7 +1270,10 @@ static void compute_pne(const uspo* o, const double* mom_centred, const int* cou
         double a = sqrt(5.0 / 3.0 * c[i].theta);
         double kr = c[i].lam * sqrt(g2[0]) / c[i].rho;
         double kt = c[i].lam * sqrt(g2[1]) / c[i].T;
-        double ku = c[i].lam * sqrt(g2[2]) / (c[i].umag > a ? c[i].umag : a);
+        /* Eq. 18 for |u|: over max(|u|, a) or, as printed, over |u| */
+        double gu = c[i].lam * sqrt(g2[2]);
+        double qu = g->gll_u == 1 ? c[i].umag : (c[i].umag > a ? c[i].umag : a);
+        double ku = gu > 0.0 ? (qu > 0.0 ? gu / qu : INFINITY) : 0.0;
         double kn = kr;
         if (kt > kn) kn = kt;
         if (ku > kn) kn = ku;
@@ -1334,6 +1337,7 @@ static int check_config(const uspo_config* g)
     }
     if (g->scheme != 0 && g->scheme != 1) return -1;
     if (g->es_mode != 0 && g->es_mode != 1) return -1;
+    if (g->gll_u != 0 && g->gll_u != 1) return -1;
     if (g->es_mode == 1 && !(g->Pr > 0.0 && g->Pr != 1.0)) return -1;
     /* SP-ESBGK has no added particles: P_ne fixed at 0 */
     if (g->scheme == 1 && !(g->pne_mode == 0 && g->pne_fixed == 0.0)) return -1;

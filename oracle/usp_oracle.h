@@ -67,6 +67,9 @@ typedef struct {
      * Eq. 29-30 (the paper); 1 = its expectation over that time
      * distribution, one Gaussian per cell with the same second moments */
     int es_mode;
+    /* velocity term of Eq. 18: 0 = lambda |grad |u|| / max(|u|, sqrt(5 theta
+     * / 3)); 1 = lambda |grad |u|| / |u| as printed */
+    int gll_u;
 } uspo_config;
 
 /* per-cell state record: centred moments, raw sums, averaged raw sums of f^n,

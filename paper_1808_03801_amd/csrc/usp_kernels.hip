@@ -98,7 +98,11 @@ __global__ void fields_kernel(Batch B, int init)
             const double a = sqrt(5.0 / 3.0 * me.theta);
             const double kr = me.lam * sqrt(g2[0]) / me.rho;
             const double kt = me.lam * sqrt(g2[1]) / me.T;
-            const double ku = me.lam * sqrt(g2[2]) / (me.umag > a ? me.umag : a);
+            // Eq. 18 for |u|: over max(|u|, a), or over |u| as printed (a
+            // cell at rest in a velocity gradient is then fully rarefied)
+            const double gu = me.lam * sqrt(g2[2]);
+            const double qu = I.gll_u == 1 ? me.umag : (me.umag > a ? me.umag : a);
+            const double ku = gu > 0.0 ? (qu > 0.0 ? gu / qu : INFINITY) : 0.0;
             double kn = kr;
             if (kt > kn) kn = kt;
             if (ku > kn) kn = ku;

@@ -52,6 +52,9 @@ SCHEME_USP, SCHEME_SP = 0, 1
 # f_G(t) of step 6: alpha at a per-particle time sample (Eq. 29-32), or its
 # expectation over the time distribution (one Gaussian per cell)
 ES_SAMPLED, ES_MEAN = 0, 1
+# velocity term of the GLL Knudsen number (Eq. 18): lambda |grad |u|| over
+# max(|u|, sound speed) (the criterion's authors' convention) or over |u|
+GLL_U_SOUND, GLL_U_LITERAL = 0, 1
 
 FACE_XLO, FACE_XHI, FACE_YLO, FACE_YHI = 0, 1, 2, 3
 
@@ -154,6 +157,7 @@ class Problem:
     plate_T: float = 273.0
     scheme: int = SCHEME_USP
     es_mode: int = ES_SAMPLED
+    gll_u: int = GLL_U_SOUND
     meta: dict = field(default_factory=dict)
 
     @property

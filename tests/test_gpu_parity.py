@@ -89,6 +89,11 @@ def _cases():
             ncell=120, ppc=200, Kn=1e-2, seed=30).replace(es_mode=P.ES_MEAN),
         "c1_esmean_fp64": lambda: P.couette_1d(ncell=40, ppc=100, seed=31).replace(
             es_mode=P.ES_MEAN),
+        # the GLL velocity term over |u| as printed (cells near the channel's
+        # middle, at rest, become fully rarefied)
+        "c1_gll_literal_fp64": lambda: P.couette_1d(ncell=40, ppc=100, seed=32,
+                                                    pne_mode=P.PNE_GLL_INST).replace(
+            gll_u=P.GLL_U_LITERAL),
         # the SP-ESBGK baseline (Table 1)
         "c1_sp_fp64": lambda: P.sp_esbgk(P.couette_1d(ncell=40, ppc=100, seed=25)),
         "cavity_sp_fp32": lambda: P.sp_esbgk(P.cavity_2d(Kn=0.01, n=16, ppc=80, seed=26)),
