@@ -39,7 +39,9 @@
  * rounded; the added-particle weight is r_p (dt J/2) / (f_e min(1, nu_ES dt)),
  * which equals Eq. 26 when nu_ES dt >= 1; selection is a per-particle
  * Bernoulli trial at the rate of Eq. 9; the particles kept by Eq. 28 are the
- * selected ones with the smallest random rank keys.
+ * selected ones with the smallest random rank keys; the velocity term of
+ * the GLL Knudsen number (Eq. 18) is taken over max(|u|, sqrt(5 theta / 3))
+ * unless gll_u asks for |u| as printed.
  *
  * The SP-ESBGK baseline of Table 1 (scheme 1) is the same step with P_ne
  * fixed at 0 (no added particles, Eq. 33 divisors 1), N_s of Eq. 9 particles
