@@ -90,6 +90,8 @@ def lib():
         L.uspo_test_pne.argtypes = [C.POINTER(Config), dp, dp]
         L.uspo_test_inject.argtypes = [C.POINTER(Config), C.c_int, C.c_int, C.c_int, C.c_int, dp,
                                        C.c_int]
+        L.uspo_get_sort.restype = C.c_longlong
+        L.uspo_get_sort.argtypes = [C.c_void_p, ip, C.POINTER(C.c_longlong)]
         _lib = L
     return _lib
 
@@ -212,6 +214,18 @@ class Oracle:
         out = np.zeros((self.ncell, NDIAG))
         lib().uspo_get_diag(self.h, _dp(out))
         return out
+
+    def get_sort(self):
+        """the last step-3 sort: (counts per cell after it, place of every
+        sorted particle in the sequence before it), or None before a step"""
+        L = lib()
+        n = L.uspo_get_sort(self.h, None, None)
+        if n < 0:
+            return None
+        counts = np.zeros(self.ncell, np.int32)
+        perm = np.zeros(max(n, 1), np.int64)
+        L.uspo_get_sort(self.h, _ip(counts), perm.ctypes.data_as(C.POINTER(C.c_longlong)))
+        return counts, perm[:n]
 
 
 # ---- pieces --------------------------------------------------------------

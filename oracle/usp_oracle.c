@@ -177,6 +177,11 @@ struct uspo {
     double* pprev; /* P_ne^{n-1} */
     double* diag; /* [ncell][NDIAG] */
     int n_samples, step, error;
+    /* the stable sort of the last step 3: particles per cell after it, and
+     * for each sorted particle its place in the sequence before it */
+    int* sort_cnt;
+    long long* sort_perm;
+    long long sort_n;
 };
 
 static uint32_t g_key(const uspo_config* g, int i) { return i == 0 ? g->seed_lo : g->seed_hi; }
@@ -367,85 +372,6 @@ static void psi_basis(const double c[3], const double U[3], double sq, double th
     psi[4] = (C[0] * C[0] + C[1] * C[1] + C[2] * C[2]) / (2.0 * theta) - 1.5;
 }
 
-/* The same constraint (zero mass, momentum and energy of the batch) met by
- * the smallest weight change that also leaves the batch's stress and heat
- * flux sums untouched: the change is a combination of the 5 conserved
- * functions psi and the 8 functions phi of the stress (traceless second
- * order: X0 X1, X0 X2, X1 X2, X0^2 - X1^2, X1^2 - X2^2) and heat flux
- * (X_i (|X|^2 / 2 - 5/2)), X = C / sqrt(theta), with sum dw psi = -sum w psi
- * and sum dw phi = 0 (a 13x13 Gram system, Cholesky).  The plain projection
- * above removes the part of the batch's stress that happens to lie in the
- * span of psi over the batch's own velocities, about 5 / N_a of it, which
- * lowers the viscosity by that fraction; this one does not.  Batches of
- * fewer than 13 particles, or with a pivot not above 1e-10 of the first
- * diagonal entry, are left unchanged. */
-static void basis13(const double c[3], const double U[3], double sq, double a[13])
-{
-    const double X0 = (c[0] - U[0]) / sq, X1 = (c[1] - U[1]) / sq, X2 = (c[2] - U[2]) / sq;
-    const double h = 0.5 * (X0 * X0 + X1 * X1 + X2 * X2);
-    a[0] = 1.0;
-    a[1] = X0;
-    a[2] = X1;
-    a[3] = X2;
-    a[4] = h - 1.5;
-    a[5] = X0 * X1;
-    a[6] = X0 * X2;
-    a[7] = X1 * X2;
-    a[8] = X0 * X0 - X1 * X1;
-    a[9] = X1 * X1 - X2 * X2;
-    a[10] = X0 * (h - 2.5);
-    a[11] = X1 * (h - 2.5);
-    a[12] = X2 * (h - 2.5);
-}
-
-static int project_batch13(const uspo_config* g, part* p, int n, const double U[3], double theta)
-{
-    enum { M = 13 };
-    if (n < M) return 0;
-    const double sq = sqrt(theta);
-    double G[M][M], b[M], a[M];
-    memset(G, 0, sizeof(G));
-    memset(b, 0, sizeof(b));
-    for (int k = 0; k < n; ++k) {
-        basis13(p[k].c, U, sq, a);
-        for (int i = 0; i < M; ++i) {
-            if (i < 5) b[i] -= p[k].w * a[i];
-            for (int j = 0; j <= i; ++j) G[i][j] += a[i] * a[j];
-        }
-    }
-    double L[M][M];
-    memset(L, 0, sizeof(L));
-    for (int i = 0; i < M; ++i)
-        for (int j = 0; j <= i; ++j) {
-            double t = G[i][j];
-            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
-            if (i == j) {
-                if (!(t > 1e-10 * G[0][0])) return -1;
-                L[i][i] = sqrt(t);
-            } else {
-                L[i][j] = t / L[j][j];
-            }
-        }
-    double y[M], mu[M];
-    for (int i = 0; i < M; ++i) {
-        double t = b[i];
-        for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
-        y[i] = t / L[i][i];
-    }
-    for (int i = M - 1; i >= 0; --i) {
-        double t = y[i];
-        for (int k = i + 1; k < M; ++k) t -= L[k][i] * mu[k];
-        mu[i] = t / L[i][i];
-    }
-    for (int k = 0; k < n; ++k) {
-        basis13(p[k].c, U, sq, a);
-        double d = 0.0;
-        for (int i = 0; i < M; ++i) d += a[i] * mu[i];
-        p[k].w = st(g, p[k].w + d);
-    }
-    return 1;
-}
-
 static int project_batch(const uspo_config* g, part* p, int n, const double U[3], double theta)
 {
     if (n < 5) return 0;
@@ -530,7 +456,6 @@ static int spawn(const uspo* o, int batch, int cell, const cellf* f, double pne,
         pl_push(L, q);
     }
     if (g->spawn_projection == 1) project_batch(g, L->p + (L->n - na), na, f->U, f->theta);
-    if (g->spawn_projection == 2) project_batch13(g, L->p + (L->n - na), na, f->U, f->theta);
     return na;
 }
 
@@ -791,6 +716,7 @@ static int inject_one(const uspo_config* g, int step, int c, int face, int k, in
 
 typedef struct {
     int dest, dy, dx, slot;
+    long long pre; /* place in the sequence before the sort */
     part q;
 } sentry;
 
@@ -1337,6 +1263,14 @@ static int check_config(const uspo_config* g)
         if (g->dim != 2 || !(g->plate_x > g->x0 && g->plate_x < g->x1)) return -1;
         if (!(g->plate_ylo <= g->plate_yhi) || !(g->plate_T > 0.0)) return -1;
     }
+    /* every mode switch takes one of its listed values */
+    if (g->pne_mode < 0 || g->pne_mode > 2) return -1;
+    if (g->weight_mode != 0 && g->weight_mode != 1) return -1;
+    if (g->conserve_mode != 0 && g->conserve_mode != 1) return -1;
+    if (g->jmom_mode != 0 && g->jmom_mode != 1) return -1;
+    if (g->spawn_projection != 0 && g->spawn_projection != 1) return -1;
+    if (g->avg_init != 0 && g->avg_init != 1) return -1;
+    if (g->n_avg < 1) return -1;
     if (g->scheme != 0 && g->scheme != 1) return -1;
     if (g->es_mode != 0 && g->es_mode != 1) return -1;
     if (g->gll_u != 0 && g->gll_u != 1) return -1;
@@ -1363,6 +1297,9 @@ static uspo* alloc_uspo(const uspo_config* cfg)
     o->pcur = (double*)calloc(nc, sizeof(double));
     o->pprev = (double*)calloc(nc, sizeof(double));
     o->diag = (double*)calloc(nc * USPO_NDIAG, sizeof(double));
+    o->sort_cnt = (int*)calloc(nc, sizeof(int));
+    o->sort_perm = NULL;
+    o->sort_n = -1;
     return o;
 }
 
@@ -1436,6 +1373,8 @@ void uspo_destroy(uspo* o)
     free(o->pcur);
     free(o->pprev);
     free(o->diag);
+    free(o->sort_cnt);
+    free(o->sort_perm);
     free(o);
 }
 
@@ -1471,7 +1410,7 @@ static void one_step(uspo* o)
         total += o->cell[c].n + t;
     }
     sentry* e = (sentry*)malloc(sizeof(sentry) * (size_t)(total + 1));
-    long long k = 0;
+    long long k = 0, pre0 = 0;
     int perx = g->face_kind[0] == 2, pery = g->face_kind[2] == 2;
     for (int c = 0; c < nc; ++c) {
         int clamped = 0, gone = 0, n = o->cell[c].n;
@@ -1496,20 +1435,37 @@ static void one_step(uspo* o)
             e[k].dy = min_image(sy - dy, g->ny, pery);
             e[k].dx = min_image(sx - dx, g->nx, perx);
             e[k].slot = s;
+            e[k].pre = pre0 + s;
             e[k].q = q;
             ++k;
         }
+        pre0 += n + ninj[4 * c] + ninj[4 * c + 1] + ninj[4 * c + 2] + ninj[4 * c + 3];
         o->diag[(size_t)USPO_NDIAG * c + D_CLAMP] = clamped;
         o->diag[(size_t)USPO_NDIAG * c + D_NGONE] = gone;
         o->cell[c].n = 0;
     }
     free(ninj);
     qsort(e, (size_t)k, sizeof(sentry), cmp_entry);
-    for (long long i = 0; i < k; ++i) pl_push(&o->cell[e[i].dest], e[i].q);
+    free(o->sort_perm);
+    o->sort_perm = (long long*)malloc(sizeof(long long) * (size_t)(k + 1));
+    o->sort_n = k;
+    for (int c = 0; c < nc; ++c) o->sort_cnt[c] = 0;
+    for (long long i = 0; i < k; ++i) {
+        pl_push(&o->cell[e[i].dest], e[i].q);
+        o->sort_perm[i] = e[i].pre;
+        o->sort_cnt[e[i].dest]++;
+    }
     free(e);
 
     /* steps 4-8 */
     for (int c = 0; c < nc; ++c) relax_cell(o, c, &o->cell[c], o->diag + (size_t)USPO_NDIAG * c);
+    /* a moment of f^{n+1} that is not finite poisons the instance (sticky) */
+    if (o->error == 0)
+        for (size_t i = 0; i < (size_t)nc * USPO_MOM; ++i)
+            if (!isfinite(o->raw[i])) {
+                o->error = -9;
+                break;
+            }
 
     /* Eq. 34 */
     if (o->step >= g->avg_start) {
@@ -1525,8 +1481,9 @@ static void one_step(uspo* o)
     o->step++;
 }
 
-/* A capacity error is sticky: the instance takes no further steps (its
- * cells may already hold more particles than the configuration allows). */
+/* A capacity (-3) or non-finite (-9) error is sticky: the instance takes no
+ * further steps (its cells may already hold more particles than the
+ * configuration allows, or moments that are not numbers). */
 int uspo_step(uspo* o, int nsteps)
 {
     for (int i = 0; i < nsteps && o->error == 0; ++i) one_step(o);
@@ -1594,6 +1551,7 @@ int uspo_set_state(uspo* o, const int* counts, const double* parts, const double
     o->step = step;
     o->n_samples = n_samples;
     o->error = 0;
+    o->sort_n = -1;
     if (cellstate) {
         for (int c = 0; c < o->ncell; ++c) {
             const double* cs = cellstate + (size_t)USPO_CS * c;
@@ -1646,6 +1604,21 @@ int uspo_get_diag(const uspo* o, double* out)
 {
     memcpy(out, o->diag, sizeof(double) * USPO_NDIAG * (size_t)o->ncell);
     return 0;
+}
+
+/* The stable counting sort of the last step's step 3 (by new cell; within a
+ * cell by source offset, then source slot): counts [ncell] of the sorted
+ * particles per cell (the particles of f-tilde^*), perm [N] for each sorted
+ * particle its place in the sequence before the sort (cells in order, each
+ * with its particles present, then its step-2 particles, then those that
+ * entered through open faces; particles that left keep their place).
+ * Returns N, or -1 before the first step; either array may be NULL. */
+long long uspo_get_sort(const uspo* o, int* counts, long long* perm)
+{
+    if (o->sort_n < 0) return -1;
+    if (counts) memcpy(counts, o->sort_cnt, sizeof(int) * (size_t)o->ncell);
+    if (perm && o->sort_n > 0) memcpy(perm, o->sort_perm, sizeof(long long) * (size_t)o->sort_n);
+    return o->sort_n;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -96,6 +96,9 @@ int uspo_set_state(uspo* o, const int* counts, const double* parts, const double
                    int step, int n_samples);
 int uspo_get_fields(const uspo* o, int which, double* out);
 int uspo_get_diag(const uspo* o, double* out);
+/* the last step-3 sort: counts [ncell] per cell after it, perm [N] place of
+ * each sorted particle in the sequence before it; returns N (-1: no step) */
+long long uspo_get_sort(const uspo* o, int* counts, long long* perm);
 
 /* pieces exposed for pinning */
 void uspo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -105,11 +105,13 @@ def _sort_reference(pb, st):
         for s in range(st.counts[c]):
             d, r = O.advect(pb, st.parts[off[c] + s], c, s, st.step)
             sx, sy, dx_, dy_ = c % pb.nx, c // pb.nx, d % pb.nx, d // pb.nx
-            ent.append(((d, mi(sy - dy_, pb.ny, per_y), mi(sx - dx_, pb.nx, per_x), s), r, d))
+            ent.append(((d, mi(sy - dy_, pb.ny, per_y), mi(sx - dx_, pb.nx, per_x), s), r, d,
+                        off[c] + s))
     ent.sort(key=lambda e: e[0])
     counts = np.bincount([e[2] for e in ent], minlength=pb.ncell)
     pos = np.array([[e[1][0], e[1][1]] for e in ent])
-    return counts, pos
+    perm = np.array([e[3] for e in ent], np.int64)
+    return counts, pos, perm
 
 
 @pytest.mark.parametrize("which", ["couette", "box", "cavity", "sod"])
@@ -130,10 +132,15 @@ def test_stable_sort_matches_brute_force(which):
     pb = pb.replace(pne_mode=P.PNE_FIXED, pne_fixed=0.0)
     o = O.Oracle(pb)
     st = o.get_state()
-    counts, pos = _sort_reference(pb, st)
+    counts, pos, perm = _sort_reference(pb, st)
+    assert o.get_sort() is None
     o.step(1)
     st1 = o.get_state()
     assert np.array_equal(st1.counts, counts)
+    # the recorded sort: counts after it and each particle's place before it
+    scnt, sperm = o.get_sort()
+    assert np.array_equal(scnt, counts)
+    assert np.array_equal(sperm, perm)
     if pb.dim == 2:
         assert np.array_equal(st1.parts[:, 0], pos[:, 0])
     assert np.array_equal(st1.parts[:, 1], pos[:, 1])
