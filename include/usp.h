@@ -18,9 +18,10 @@
  *  - Every function returns a usp_status; 0 is success.  The text of the last
  *    error of a context is returned by usp_last_error.
  *  - Argument errors are reported synchronously.  Errors raised inside the
- *    kernels (capacity, window) are sticky per instance and reported by the
- *    next usp_sync / usp_get_* call on it; a failed instance refuses further
- *    steps with USP_ESTATE, other instances continue.
+ *    kernels (capacity, window, non-finite moments) are sticky per instance
+ *    and reported by the next usp_sync / usp_get_* call on it; a failed
+ *    instance refuses further steps with USP_ESTATE, other instances
+ *    continue.
  *  - The context owns all device memory it allocates (through the caller's
  *    allocator if one is given).  The caller owns every host buffer passed in.
  *  - All work is enqueued on the context's HIP stream; usp_step returns
@@ -48,7 +49,8 @@ typedef enum {
     USP_EWINDOW = -4,   /* a particle moved farther than the sort window (poisoned) */
     USP_EDEVICE = -5,   /* a HIP runtime call failed */
     USP_ESTATE = -7,    /* instance unknown, freed or poisoned */
-    USP_ENOLIB = -8     /* built without device support */
+    USP_ENOLIB = -8,    /* built without device support */
+    USP_ENONFINITE = -9 /* a cell moment became infinite or NaN (instance poisoned) */
 } usp_status;
 
 enum { USP_BC_DIFFUSE = 0, USP_BC_SPECULAR = 1, USP_BC_PERIODIC = 2, USP_BC_OPEN = 3 };
@@ -240,6 +242,43 @@ usp_status usp_moments(usp_ctx* ctx, int id, int which, usp_moments_view* out);
  * step-8 moments, step 2, advection, bin counts, bin offsets, writes). */
 usp_status usp_set_diag(usp_ctx* ctx, int id, int on);
 usp_status usp_get_diag(usp_ctx* ctx, int id, double* out);
+
+/* The stable counting sort of the last time step's step 3 (Table 2: the
+ * particles sorted into cells after advection, "similar to DSMC"): the
+ * particles of f-tilde^* that Eq. 33 sums, cell by cell, each cell in
+ * canonical order (source offset in the sort window, then source slot).
+ * cell_offsets [ncell + 1]: first sorted particle of each cell
+ * (cell_offsets[ncell] = N).  perm [N] (may be NULL, to learn N first): for
+ * each sorted particle its place in the sequence before the sort, which
+ * lists the cells in order and, per cell, its particles of f^n in canonical
+ * order, then its step-2 particles, then the particles that entered through
+ * its open faces (those that left through an open face keep their place).
+ * Valid after a usp_step call made with diagnostics on (usp_set_diag; the
+ * record is kept in its buffers); USP_ESTATE otherwise or after
+ * usp_set_state.  Host arrays, owned by the caller; synchronises. */
+usp_status usp_get_sort(usp_ctx* ctx, int id, int32_t* cell_offsets, int32_t* perm);
+
+/* Counters of one instance (synchronises).  live, step and error always;
+ * diag = 1 when the rest describes the last time step (a usp_step call made
+ * with diagnostics on), else 0 and the rest is zero.  added: particles of
+ * the Eq. 25 batches of steps 2, 4 and 7; selected / reassigned / deleted:
+ * step 5 (Eq. 9, 28); entered / left: through open faces; clamped: wall
+ * traces stopped after 16 hits; es_fallback: step-6 Gaussians whose FP64
+ * Cholesky factor fell back to theta I; cells_invalid: cells with fewer than
+ * two particles or no positive mass or temperature (not relaxed);
+ * mass_fail / energy_fail: cells whose conservation correction was skipped;
+ * whole_cell: cells corrected by the whole-cell shift and scale. */
+typedef struct {
+    long long live;
+    int step;
+    int error;
+    int diag;
+    long long added[3];
+    long long selected, reassigned, deleted;
+    long long entered, left, clamped, es_fallback;
+    long long cells_invalid, mass_fail, energy_fail, whole_cell;
+} usp_stats_t;
+usp_status usp_stats(usp_ctx* ctx, int id, usp_stats_t* out);
 
 /* Launch shape: threads per cell workgroup.  The cell kernel keeps a cell's
  * particles in the registers of 256 threads, so 256 (or 0 for the default)

@@ -3,4 +3,5 @@
 
 namespace usp {
 USP_CELL_ALL(float, 1, false)
+USP_CELL_W6(float, 1)
 }  // namespace usp

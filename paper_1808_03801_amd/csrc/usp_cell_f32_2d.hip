@@ -3,4 +3,5 @@
 
 namespace usp {
 USP_CELL_ALL(float, 2, false)
+USP_CELL_W6(float, 2)
 }  // namespace usp

@@ -3,4 +3,5 @@
 
 namespace usp {
 USP_CELL_ALL(double, 1, false)
+USP_CELL_W6(double, 1)
 }  // namespace usp

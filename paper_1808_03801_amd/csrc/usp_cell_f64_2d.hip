@@ -3,4 +3,5 @@
 
 namespace usp {
 USP_CELL_ALL(double, 2, false)
+USP_CELL_W6(double, 2)
 }  // namespace usp

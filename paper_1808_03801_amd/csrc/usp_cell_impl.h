@@ -1,14 +1,16 @@
 // gfx950 cell kernel of the USP-ESBGK time step (arXiv 1808.03801, Table 2).
 //
-// One 256-thread workgroup owns one cell at a time.  The cell's particles
-// live in registers: particle j of the cell is held by thread j % 256 in
-// register slot j / 256 (PPT slots per thread, fully unrolled), so every
-// per-particle phase runs without LDS traffic and with PPT independent
-// instruction streams per thread.  LDS holds only tables: the gather map, bin
-// tile counts, the rank histogram, reduction scratch, the staging of the Gram
-// sums of added batches and the cell scalars.  PPT is a template parameter
-// (1, 2, 4, 6 or 8); the 4|6 kernel reruns a cell that needs more than 1024
-// slots with 6 per thread in the same workgroup.
+// One workgroup of NT threads owns one cell: 256 threads (four waves) for
+// the workgroup shapes, one wave of 64 threads for the wave shapes.  The
+// cell's particles live in registers: particle j of the cell is held by
+// thread j % NT in register slot j / NT (PPT slots per thread, fully
+// unrolled), so every per-particle phase runs without LDS traffic and with
+// PPT independent instruction streams per thread.  LDS holds only tables:
+// the gather map, bin tile counts, the rank histogram, reduction scratch, the
+// staging of the Gram sums of added batches and the cell scalars.  PPT is a
+// template parameter (1, 2, 4, 6 or 8); the 4|6 kernel reruns a cell that
+// needs more than 1024 slots with 6 per thread in the same workgroup.  A
+// one-wave cell synchronises its lanes through LDS alone (no barrier).
 //
 // Phases for one cell (mode bits select them):
 //   gather    read the cell's arrivals from the neighbours' bins in canonical
@@ -31,7 +33,6 @@
 
 namespace usp {
 
-constexpr int MAX_NW = 4;  // waves per workgroup (256 threads)
 constexpr int FAR_BIN = 0xFFFF;
 constexpr uint32_t FAR_PENDING = 0xFFFEu;  // leaves the sort window; far list not yet written
 constexpr uint32_t FARBIT = 0x80000000u;
@@ -42,7 +43,7 @@ enum { FT_KEEP = 0, FT_REASSIGN = 1, FT_DELETE = 2, FT_SEL = 3, FT_EMPTY = 4 };
 struct Lds {
     uint32_t* srcmap;  // [cap] source index of each gathered position
     uint16_t* tiles;   // [cap / 64][nb]
-    uint32_t* hist;    // [KTH_BINS]
+    uint32_t* hist;    // [lds_dims(NT).kth]
     uint32_t* wtot;    // [64] per-wave scan totals
     double* red;       // [NW][24]
     uint32_t* run_pre;
@@ -55,7 +56,7 @@ struct Lds {
     uint32_t* fib;
     uint32_t* fcount;
     double* sc;
-    double* psb;   // [PSB][6] basis values and weight of added particles (Gram sums)
+    double* psb;   // [psb][6] basis values and weight of added particles (Gram sums)
     CellF* f;      // cell scalars shared by the workgroup
     double* mom;   // [0..12] centred, [13..25] averages, [26] energy, [27..29] momentum
     double* pend;  // [0..12] raw sums, [13..25] J-moment averages, [26] count: stored
@@ -67,8 +68,10 @@ struct Lds {
 
 static_assert(sizeof(CellF) <= 256, "cell scalars must fit their LDS slot");
 
+template <int NT>
 __device__ __forceinline__ Lds carve(unsigned char* sm, int cap, int nb)
 {
+    constexpr LdsDims D = lds_dims(NT);
     Lds L;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -78,20 +81,20 @@ __device__ __forceinline__ Lds carve(unsigned char* sm, int cap, int nb)
     };
     L.srcmap = (uint32_t*)take((size_t)cap * 4);
     L.tiles = (uint16_t*)take((size_t)(cap / 64) * nb * 2);
-    L.hist = (uint32_t*)take((size_t)KTH_BINS * 4);
+    L.hist = (uint32_t*)take((size_t)D.kth * 4);
     L.wtot = (uint32_t*)take(64 * 4);
-    L.red = (double*)take((size_t)MAX_NW * 24 * 8);
+    L.red = (double*)take((size_t)D.nw * 24 * 8);
     L.run_pre = (uint32_t*)take((size_t)(nb + 1) * 4);
     L.run_src = (uint32_t*)take((size_t)(nb + 1) * 4);
     L.run_dst = (uint32_t*)take((size_t)(nb + 1) * 4);
     L.boff = (uint32_t*)take((size_t)(nb + 1) * 4);
-    L.fkey = (uint64_t*)take((size_t)FAR_LDS * 8);
-    L.fent = (uint32_t*)take((size_t)FAR_LDS * 4);
-    L.fpos = (uint32_t*)take((size_t)FAR_LDS * 4);
-    L.fib = (uint32_t*)take((size_t)FAR_LDS * 4);
+    L.fkey = (uint64_t*)take((size_t)D.far * 8);
+    L.fent = (uint32_t*)take((size_t)D.far * 4);
+    L.fpos = (uint32_t*)take((size_t)D.far * 4);
+    L.fib = (uint32_t*)take((size_t)D.far * 4);
     L.fcount = (uint32_t*)take(16);
     L.sc = (double*)take(64 * 8);
-    L.psb = (double*)take((size_t)PSB * 6 * 8);
+    L.psb = (double*)take((size_t)D.psb * 6 * 8);
     L.f = (CellF*)take(sizeof(CellF));
     L.mom = (double*)take(32 * 8);
     L.pend = (double*)take(32 * 8);
@@ -103,18 +106,35 @@ __device__ __forceinline__ Lds carve(unsigned char* sm, int cap, int nb)
 // a value known to be equal in all lanes, made visibly uniform (scalar)
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Make the workgroup's LDS writes visible to all its threads.  A one-wave
+// workgroup runs its lanes in lock step, so completing its own LDS
+// operations (and keeping the compiler from moving LDS accesses across) is
+// enough; larger workgroups need the barrier.
+template <int NT>
+__device__ __forceinline__ void wg_sync()
+{
+    if constexpr (NT == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <int NT, int K>
 __device__ __forceinline__ void bsum(double (&v)[K], double* red, int tid)
 {
     constexpr int NW = NT / 64;
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    if constexpr (NW == 1) return;  // one wave: every lane holds the total
     const int lane = tid & 63, wave = tid >> 6;
-    __syncthreads();
+    wg_sync<NT>();
     if (lane == 0)
 #pragma unroll
         for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
-    __syncthreads();
+    wg_sync<NT>();
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         double s = 0.0;
@@ -129,10 +149,11 @@ __device__ __forceinline__ double bmin(double v, double* red, int tid)
 {
     constexpr int NW = NT / 64;
     v = wave_min(v);
+    if constexpr (NW == 1) return v;
     const int lane = tid & 63, wave = tid >> 6;
-    __syncthreads();
+    wg_sync<NT>();
     if (lane == 0) red[wave] = v;
-    __syncthreads();
+    wg_sync<NT>();
     double m = red[0];
 #pragma unroll
     for (int w = 1; w < NW; ++w) m = fmin(m, red[w]);
@@ -146,15 +167,25 @@ __device__ __forceinline__ int phys_scan(const bool (&flag)[PPT], int (&pre)[PPT
 {
     constexpr int NW = NT / 64;
     const int lane = tid & 63, wave = tid >> 6;
+    if constexpr (NW == 1) {
+        int base = 0;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const uint64_t m = __ballot(flag[k]);
+            pre[k] = base + __popcll(m & lanemask_lt(lane));
+            base += __popcll(m);
+        }
+        return base;
+    }
     int wpre[PPT];
-    __syncthreads();
+    wg_sync<NT>();
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const uint64_t m = __ballot(flag[k]);
         wpre[k] = __popcll(m & lanemask_lt(lane));
         if (lane == 0) wtot[k * NW + wave] = (uint32_t)__popcll(m);
     }
-    __syncthreads();
+    wg_sync<NT>();
     int base = 0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -315,6 +346,7 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
             P.st[k] = (uint32_t)FT_KEEP | ((uint32_t)(ls + q) << 8);
         }
     }
+    constexpr int PSB = lds_dims(NT).psb;
     if (I.proj && na >= 5) {
         // Gram matrix and right-hand side summed in batch order (the order
         // the batch was drawn in), independent of where the batch sits in
@@ -328,7 +360,7 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
         double acc4[4] = {0.0, 0.0, 0.0, 0.0};
         bool mine = false;
         for (int q0 = 0; q0 < na; q0 += PSB) {
-            __syncthreads();
+            wg_sync<NT>();
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const int j = k * NT + tid;
@@ -344,7 +376,7 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
                     ps[5] = (double)P.w[k];
                 }
             }
-            __syncthreads();
+            wg_sync<NT>();
             if (tid < 20) {
                 // four running sums over q mod 4 (a fixed order: the loads of
                 // successive particles overlap), joined after the last chunk
@@ -361,9 +393,9 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
                     if (q + u < nq) acc4[u] += L.psb[6 * (q + u) + ea] * L.psb[6 * (q + u) + eb];
             }
         }
-        __syncthreads();
+        wg_sync<NT>();
         if (tid < 20) L.sc[tid] = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
-        __syncthreads();
+        wg_sync<NT>();
         // only the waves holding the batch solve and update
         if (__ballot(mine) == 0) return na;
         double g[20];
@@ -555,22 +587,25 @@ __device__ __forceinline__ int resample_one(const InstDev& I, int cell, int slot
 }
 
 // k-th smallest (1-based) rank key among the selected particles.  The keys
-// are 21 random bits over the 11-bit slot, so an 11-bit histogram of the top
-// bits leaves about nsel / 2048 keys in the bucket that holds the k-th; those
-// are collected (into the gather map, free during the relaxation) and ranked
+// are 21 random bits over the 11-bit slot, so a histogram of the top bits
+// (11 bits for 256-thread cells, 6 for one-wave cells of at most 512
+// particles) leaves a few keys in the bucket that holds the k-th; those are
+// collected (into the gather map, free during the relaxation) and ranked
 // exactly by wave 0.  Keys are distinct (they end in the slot).
 template <int NT, typename real, int DIM, int PPT>
 __device__ uint32_t kth_key_r(const Parts<real, DIM, PPT>& P, const Lds& L, int kth, int nuse,
                               int tid)
 {
-    constexpr int NB = KTH_BINS;
+    constexpr int NB = lds_dims(NT).kth;
+    constexpr int SH = NB == 64 ? 26 : 21;  // bucket = the key's top log2(NB) bits
+    static_assert((1 << (32 - SH)) == NB, "bucket bits");
     for (int b = tid; b < NB; b += NT) L.hist[b] = 0u;
     if (tid == 0) L.fcount[1] = 0u;
-    __syncthreads();
+    wg_sync<NT>();
 #pragma unroll
     for (int k = 0; k < PPT; ++k)
-        if (k * NT < nuse && fate(P, k) == FT_SEL) atomicAdd(&L.hist[P.key[k] >> 21], 1u);
-    __syncthreads();
+        if (k * NT < nuse && fate(P, k) == FT_SEL) atomicAdd(&L.hist[P.key[k] >> SH], 1u);
+    wg_sync<NT>();
     if (tid < 64) {
         // lane l owns buckets [32 l, 32 l + 32)
         uint32_t s = 0;
@@ -596,15 +631,15 @@ __device__ uint32_t kth_key_r(const Parts<real, DIM, PPT>& P, const Lds& L, int 
             L.wtot[63] = run;                              // keys below that bucket
         }
     }
-    __syncthreads();
+    wg_sync<NT>();
     const uint32_t bucket = L.wtot[62];
     const int rem = kth - (int)L.wtot[63];
     uint32_t* cand = L.srcmap;
 #pragma unroll
     for (int k = 0; k < PPT; ++k)
-        if (k * NT < nuse && fate(P, k) == FT_SEL && (P.key[k] >> 21) == bucket)
+        if (k * NT < nuse && fate(P, k) == FT_SEL && (P.key[k] >> SH) == bucket)
             cand[atomicAdd(&L.fcount[1], 1u)] = P.key[k];
-    __syncthreads();
+    wg_sync<NT>();
     if (tid < 64) {
         const int m = (int)L.fcount[1];
         for (int i = tid; i < m; i += 64) {
@@ -614,7 +649,7 @@ __device__ uint32_t kth_key_r(const Parts<real, DIM, PPT>& P, const Lds& L, int 
             if (r == rem - 1) L.wtot[61] = ki;
         }
     }
-    __syncthreads();
+    wg_sync<NT>();
     return L.wtot[61];
 }
 
@@ -690,8 +725,8 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     const int nsamp = ctl[CTL_NSAMP];
     const int nb = I.nb;
     constexpr int CAP = PPT * NT;
-    static_assert(NT >= MAX_BINS, "the gather takes one window bin per thread");
-    const Lds L = carve(smem, carve_cap, nb);
+    constexpr int FAR_LDS = lds_dims(NT).far;
+    const Lds L = carve<NT>(smem, carve_cap, nb);
     const int ix = c % I.nx, iy = c / I.nx;
     const bool per_x = I.face_kind[0] == 2, per_y = I.face_kind[2] == 2;
     uint32_t errbits = 0;
@@ -726,7 +761,8 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     // ---- gather: window bins of the neighbours, then far arrivals.  All
     // global loads of this part are issued before any of them is waited for:
     // the per-cell inputs of the lane-0 sections, the far-list length and the
-    // neighbours' bin offsets (nb <= 256 bins: one per thread).
+    // neighbours' bin offsets (nb <= 256 bins: one per thread of a 256-thread
+    // cell, a few per lane of a one-wave cell).
     double pv = 0.0;
     if (tid < 41) {
         if (tid < 13) {
@@ -742,8 +778,13 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     const int nfar_all = I.far_n[cur];
     {
         const uint32_t* tin = I.tab[cur];
-        const int b = tid;
-        uint32_t len = 0, base = 0;
+        constexpr int BPT = (MAX_BINS + NT - 1) / NT;  // window bins per thread
+        uint32_t len[BPT], base[BPT];
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+        const int b = q * NT + tid;
+        len[q] = 0;
+        base[q] = 0;
         if (b < nb) {
             const int oy = b / I.nbx - I.Ky, ox = b % I.nbx - I.Kx;
             int sy = iy + oy, sx = ix + ox;
@@ -760,17 +801,22 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                 const int s = sy * I.nx + sx;
                 const uint32_t* t = tin + (size_t)s * (nb + 1);
                 const uint32_t a0 = t[b], a1 = t[b + 1];
-                len = a1 - a0;
-                base = (uint32_t)s * (uint32_t)I.cap + a0;
+                len[q] = a1 - a0;
+                base[q] = (uint32_t)s * (uint32_t)I.cap + a0;
             }
         }
+        }
         if (tid < 41) L.pre[tid] = pv;
-        if (b < nb) {
-            L.run_pre[b] = len;
-            L.run_src[b] = base;
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int b = q * NT + tid;
+            if (b < nb) {
+                L.run_pre[b] = len[q];
+                L.run_src[b] = base[q];
+            }
         }
         if (tid == 0) L.fcount[0] = 0u;
-        __syncthreads();
+        wg_sync<NT>();
         wave0_scan(L.run_pre, nb, tid);
         if (nfar_all > 0) {
             const uint32_t* fm = I.far_meta[cur];
@@ -783,7 +829,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                     }
                 }
         }
-        __syncthreads();
+        wg_sync<NT>();
     }
     int nfc = (int)L.fcount[0];
     if (nfc > FAR_LDS) {
@@ -805,14 +851,14 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             L.fpos[k] = L.run_pre[ib] + r;
             L.fib[k] = (uint32_t)ib;
         }
-        __syncthreads();
+        wg_sync<NT>();
     }
     for (int b = tid; b < nb; b += NT) {
         uint32_t sh = 0;
         for (int k = 0; k < nfc; ++k) sh += (int)L.fib[k] <= b ? 1u : 0u;
         L.run_dst[b] = L.run_pre[b] + sh;
     }
-    __syncthreads();
+    wg_sync<NT>();
     gs.nwin = (int)L.run_pre[nb];
     gs.nfc = nfc;
     gs.n0 = gs.nwin + nfc;
@@ -824,8 +870,12 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     errbits |= gs.err;
     if (can_defer && n0 <= I.max_ppc) {
         // particles added in this launch: S0 / r_p per batch (S0 of the
-        // cell's previous moments standing in for the current one)
-        const int nbat = ((mode & MODE_RELAX) ? 2 : 0) + ((mode & MODE_MOVE) ? 1 : 0);
+        // cell's previous moments standing in for the current one).  A pass
+        // that relaxes budgets three batches whether or not it also moves:
+        // which shape relaxes a cell then does not depend on how a run is
+        // split into calls (wave and workgroup shapes add in different
+        // orders).
+        const int nbat = (mode & MODE_RELAX) ? 3 : 1;
         const double sp = fmax(L.pre[26], 0.0);
         const double est = n0 + nbat * (1.1 * sp / I.r_p + 8.0);
         if (n0 > CAP || est > (double)CAP) return defer(1);
@@ -847,7 +897,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     }
     for (int k = tid; k < nfc; k += NT)
         if ((int)L.fpos[k] < n0) L.srcmap[L.fpos[k]] = FARBIT | L.fent[k];
-    __syncthreads();
+    wg_sync<NT>();
     {
         const real* in[6];
         const real* fin[6];
@@ -871,6 +921,23 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                 P.c2[k] = src[4][e];
                 P.w[k] = src[5][e];
                 P.st[k] = (uint32_t)FT_KEEP | ((uint32_t)j << 8);
+                if (I.diag && (mode & MODE_RELAX)) {
+                    // where this particle of f-tilde^* came from (the sort's record)
+                    uint32_t scell, sslot;
+                    if (s & FARBIT) {
+                        const uint32_t* fm = I.far_meta[cur] + 3 * e;
+                        int sy = iy + ((int)(fm[1] >> 16) - 32768);
+                        int sx = ix + ((int)(fm[1] & 0xFFFFu) - 32768);
+                        if (per_y) sy = wrap(sy, I.ny);
+                        if (DIM == 2 && per_x) sx = wrap(sx, I.nx);
+                        scell = (uint32_t)(sy * I.nx + (DIM == 2 ? sx : 0));
+                        sslot = fm[2];
+                    } else {
+                        scell = (uint32_t)(e / (size_t)I.cap);
+                        sslot = I.ori[cur][e];
+                    }
+                    I.sorg[(size_t)c * I.cap + j] = ((uint64_t)scell << 32) | sslot;
+                }
             } else {
                 P.st[k] = FT_EMPTY;
             }
@@ -889,7 +956,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
         if (dg && tid == 0) {
             for (int k = 0; k < NDIAG_STEP; ++k)
                 if (k != D_N2 && k != D_CLAMP && k != D_MARG_CNT2 && k != D_NINJ &&
-                    k != D_NGONE)
+                    k != D_NGONE && k != D_NPRE)
                     dg[k] = 0.0;
             dg[D_NIN] = n0;
         }
@@ -923,7 +990,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                     f = fw;
                 }
             }
-            __syncthreads();
+            wg_sync<NT>();
         }
         mark(1);
         int flags = 0;
@@ -1180,6 +1247,10 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             double cen1[NMOM], raw1[NMOM], E1;
             moments_r<NT>(P, L, tid, uni(nphys), cen1, raw1, &E1);
             if (tid == 0) {
+                // a moment that is not a finite number poisons the instance
+                bool fin = true;
+                for (int q = 0; q < NMOM; ++q) fin = fin && isfinite(raw1[q]);
+                if (!fin) errbits |= ERR_NONFINITE;
                 L.pend[26] = (double)nlog;
                 const double ne = avg_window(I.n_avg, nsamp, I.avg_init);
                 for (int q = 0; q < NMOM; ++q) {
@@ -1298,7 +1369,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
         };
         const int nphys0 = nphys;
         move(0, nphys0, true);
-        __syncthreads();
+        wg_sync<NT>();
         const double P2 = (mode & MODE_RELAX) ? L.pre[39] : L.pre[40];
         double mc2 = __builtin_inf();
         // step 2 of the next time level
@@ -1402,7 +1473,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
         // stable ranks by bin over physical positions (tiles of 64)
         const int ntl = (nphys + 63) / 64;
         for (int q = tid; q < ntl * nb; q += NT) L.tiles[q] = 0;
-        __syncthreads();
+        wg_sync<NT>();
         const int lane = tid & 63;
         // lanes of a wave that share a bin, found bit by bit of the bin
         // index (one ballot per bit instead of one per distinct bin)
@@ -1431,15 +1502,15 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                 if (rank[k] == 0) L.tiles[tile * nb + b] = (uint16_t)__popcll(peers);
             }
         }
-        __syncthreads();
+        wg_sync<NT>();
         for (int b = tid; b < nb; b += NT) {
             uint32_t s = 0;
             for (int t = 0; t < ntl; ++t) s += L.tiles[t * nb + b];
             L.boff[b] = s;
         }
-        __syncthreads();
+        wg_sync<NT>();
         wave0_scan(L.boff, nb, tid);
-        __syncthreads();
+        wg_sync<NT>();
         for (int b = tid; b < nb; b += NT) {
             uint32_t run = L.boff[b];
             for (int t = 0; t < ntl; ++t) {
@@ -1448,7 +1519,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                 run += v;
             }
         }
-        __syncthreads();
+        wg_sync<NT>();
         mark(12);
         // write-out: each particle straight from its registers
 #pragma unroll
@@ -1462,6 +1533,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                 out[3][rbase + pos] = P.c1[k];
                 out[4][rbase + pos] = P.c2[k];
                 out[5][rbase + pos] = P.w[k];
+                if (I.diag) I.ori[1 - cur][rbase + pos] = P.st[k] >> 8;
             }
         }
         for (int b = tid; b <= nb; b += NT) tout[b] = L.boff[b];
@@ -1475,6 +1547,7 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                 dg[D_MARG_CNT2] = mc2;
                 dg[D_NINJ] = nin;
                 dg[D_NGONE] = cl[1];
+                dg[D_NPRE] = nlog;
             }
         }
     } else {
@@ -1517,13 +1590,20 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     return 0;
 }
 
-// Workgroups per CU asked of the register allocator: the kernel waits on
-// memory, LDS and barriers about half of its time, so more cells in flight
-// pay for some register spills: 4 for the 1-, 2- and 4-slot shapes (128
-// VGPRs), 3 for 4|6 (168 VGPRs); measured 9 % (C2 pair) to 32 % (cavity)
-// faster than without spills at 3 and 2 workgroups per CU.
+// Waves per SIMD asked of the register allocator (the second launch bound):
+// the kernel waits on memory, LDS and barriers about half of its time, so
+// more cells in flight pay for some register spills: 4 for the 1-, 2- and
+// 4-slot workgroup shapes (128 VGPRs), 3 for 4|6 (168 VGPRs); measured 9 %
+// (C2 pair) to 32 % (cavity) faster than without spills at 3 and 2
+// workgroups per CU.  One-wave cells: 4 waves per SIMD, 16 cells per CU.
+template <int NT, int PPT, int PPT2>
+constexpr int cell_waves_per_simd()
+{
+    return NT == 64 ? 4 : (PPT2 > 0 ? 3 : (PPT <= 4 ? 4 : 1));
+}
+
 template <typename real, int DIM, int NT, int PPT, int PPT2, bool XB>
-__global__ void __launch_bounds__(NT, (PPT2 > 0 ? 3 : (PPT <= 4 ? 4 : 1))) cell_kernel(Batch B)
+__global__ void __launch_bounds__(NT, (cell_waves_per_simd<NT, PPT, PPT2>())) cell_kernel(Batch B)
 {
     // one workgroup per cell (no loop over cells: a loop would let the
     // compiler hoist constants across the whole cell body)
@@ -1559,7 +1639,10 @@ __global__ void __launch_bounds__(NT, (PPT2 > 0 ? 3 : (PPT <= 4 ? 4 : 1))) cell_
 }
 
 // XB: the extended boundary set (open faces, the internal plate); instances
-// without them run the variant that leaves that code out
+// without them run the variant that leaves that code out.  The 6-slot wave
+// shape exists without it only: with it the compiler makes the step-2
+// added-particle routine an out-of-line call (as in the 8-slot workgroup
+// shapes), and every one-wave kernel that runs is kept free of calls.
 #define USP_CELL_INST(R, D, NT, PPT, PPT2, XB) \
     template __global__ void cell_kernel<R, D, NT, PPT, PPT2, XB>(Batch);
 #define USP_CELL_ALL(R, D, XB)            \
@@ -1567,6 +1650,8 @@ __global__ void __launch_bounds__(NT, (PPT2 > 0 ? 3 : (PPT <= 4 ? 4 : 1))) cell_
     USP_CELL_INST(R, D, 256, 2, 0, XB)    \
     USP_CELL_INST(R, D, 256, 4, 0, XB)    \
     USP_CELL_INST(R, D, 256, 4, 6, XB)    \
-    USP_CELL_INST(R, D, 256, 8, 0, XB)
+    USP_CELL_INST(R, D, 256, 8, 0, XB)    \
+    USP_CELL_INST(R, D, 64, 4, 0, XB)
+#define USP_CELL_W6(R, D) USP_CELL_INST(R, D, 64, 6, 0, false)
 
 }  // namespace usp

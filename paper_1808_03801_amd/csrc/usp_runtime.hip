@@ -45,12 +45,29 @@ struct Instance {
     size_t bytes = 0;
     bool alive = false;
     bool diag_on = false;
+    bool sort_ok = false;  // a step has run with diagnostics on since the last state load
+    // diagnostic buffers, kept while diagnostics are switched off and on
+    double* dg_mem = nullptr;
+    uint32_t* ori_mem[2] = {nullptr, nullptr};
+    uint64_t* sorg_mem = nullptr;
     int first = -1;       // first launch shape (-1: the default)
+    double mean_ppc = 0;  // particles per cell of the initial state, mean over cells
     double* fview = nullptr;  // usp_moments buffer [18][ncell]
     int top() const { return pick_shape_index(h.max_ppc); }
     // open faces or the plate: the kernel variant with the extended boundary set
     int xb() const { return (h.open_mask != 0 || h.plate) ? 1 : 0; }
-    int first_shape() const { return first >= 0 ? first : std::min(top(), TIER_FIRST); }
+    // Default first shape: cells of up to about 170 particles on average
+    // (their count grows by a third with the weighted particles, plus the
+    // added batches) go to one wave with 4 slots per lane, up to about 250
+    // (without open faces or the plate) to one wave with 6; denser instances
+    // to the workgroup shapes.
+    int default_first() const
+    {
+        if (mean_ppc * 1.4 + 16.0 <= SHAPES[SHAPE_W4].slots()) return SHAPE_W4;
+        if (!xb() && mean_ppc * 1.4 + 24.0 <= SHAPES[SHAPE_W6].slots()) return SHAPE_W6;
+        return std::min(top(), TIER_FIRST);
+    }
+    int first_shape() const { return first >= 0 ? first : default_first(); }
 };
 
 }  // namespace
@@ -208,11 +225,26 @@ usp_status validate(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb, con
     // the open-face / plate kernel variant runs in the shapes up to 256 x
     // (4 | 6) slots: its 8-slot shape is switched off (a run of it faulted
     // on the device with the cause not found)
-    if ((open || pb->plate) && pick_shape_index(nm->max_ppc) == NSHAPE - 1)
+    if ((open || pb->plate) && pick_shape_index(nm->max_ppc) == NSHAPE_WG - 1)
         return fail(ctx, USP_EINVAL,
                     "open faces or the plate: max_ppc must be at most 1365 (8-slot shape off)");
     if (open && (pb->accel[0] != 0.0 || pb->accel[1] != 0.0 || pb->accel[2] != 0.0))
         return fail(ctx, USP_EINVAL, "open faces cannot be combined with a body acceleration");
+    // every mode switch takes one of its listed values (no silent default branch)
+    if (nm->pne_mode < USP_PNE_FIXED || nm->pne_mode > USP_PNE_GLL_AVG)
+        return fail(ctx, USP_EINVAL, "unknown pne_mode");
+    if (nm->weight_mode != USP_WEIGHT_CONSISTENT && nm->weight_mode != USP_WEIGHT_LITERAL)
+        return fail(ctx, USP_EINVAL, "unknown weight_mode");
+    if (nm->conserve_mode != USP_CONSERVE_FULL && nm->conserve_mode != USP_CONSERVE_NONE)
+        return fail(ctx, USP_EINVAL, "unknown conserve_mode");
+    if (nm->jmom_mode != USP_JMOM_INST && nm->jmom_mode != USP_JMOM_AVG)
+        return fail(ctx, USP_EINVAL, "unknown jmom_mode");
+    if (nm->spawn_projection != 0 && nm->spawn_projection != 1)
+        return fail(ctx, USP_EINVAL, "spawn_projection must be 0 or 1");
+    if (nm->avg_init != 0 && nm->avg_init != 1)
+        return fail(ctx, USP_EINVAL, "avg_init must be 0 or 1");
+    if (nm->window < 0) return fail(ctx, USP_EINVAL, "window must be >= 0");
+    if (!(nm->Kn_c > 0.0)) return fail(ctx, USP_EINVAL, "Kn_c must be positive");
     if (nm->scheme != USP_SCHEME_USP && nm->scheme != USP_SCHEME_SP)
         return fail(ctx, USP_EINVAL, "unknown scheme");
     if (nm->es_mode != USP_ES_SAMPLED && nm->es_mode != USP_ES_MEAN)
@@ -266,6 +298,11 @@ usp_status with_kernel(int prec, int dim, F f)
 template <typename real, int D, bool XB>
 const void* cell_kernel_for(Shape sh)
 {
+    if (sh.nt == 64) {
+        if (sh.ppt == 4) return (const void*)cell_kernel<real, D, 64, 4, 0, XB>;
+        if constexpr (!XB) return (const void*)cell_kernel<real, D, 64, 6, 0, false>;
+        return nullptr;  // no 6-slot wave shape with open faces or the plate
+    }
     if (sh.ppt2 == 6) return (const void*)cell_kernel<real, D, 256, 4, 6, XB>;
     switch (sh.ppt) {
         case 1: return (const void*)cell_kernel<real, D, 256, 1, 0, XB>;
@@ -305,18 +342,21 @@ usp_status set_lds(usp_ctx* ctx, const void* kern, size_t lds)
     return USP_OK;
 }
 
-// the kernels of one cell pass with their dynamic LDS sizes
+// the kernels of one cell pass (the shape chain from `first`) with their
+// dynamic LDS sizes: f(position in the chain, chain, its length, shape,
+// kernel, lds bytes)
 template <typename F>
 usp_status for_each_tier(int prec, int dim, int xb, int max_nb, int first, int top, F f)
 {
-    const int lo = std::min(first, top);
-    for (int t = lo; t <= top; ++t) {
-        const Shape sh = SHAPES[t];
-        const size_t lds = lds_bytes(sh.slots(), max_nb);
+    int chain[NSHAPE];
+    const int n = shape_chain(first, top, chain);
+    for (int i = 0; i < n; ++i) {
+        const Shape sh = SHAPES[chain[i]];
+        const size_t lds = lds_bytes(sh.nt, sh.slots(), max_nb);
         usp_status st = with_kernel(prec, dim, [&](auto* rp, auto dimc) -> usp_status {
             using real = std::remove_pointer_t<decltype(rp)>;
             constexpr int D = decltype(dimc)::value;
-            return f(t, lo, sh,
+            return f(i, chain, n, sh,
                      xb ? cell_kernel_for<real, D, true>(sh) : cell_kernel_for<real, D, false>(sh),
                      lds);
         });
@@ -328,15 +368,18 @@ usp_status for_each_tier(int prec, int dim, int xb, int max_nb, int first, int t
 usp_status prepare_cell(usp_ctx* ctx, int prec, int dim, int xb, int max_nb, int first, int top)
 {
     return for_each_tier(prec, dim, xb, max_nb, first, top,
-                         [&](int, int, Shape, const void* kern, size_t lds) {
+                         [&](int, const int*, int, Shape, const void* kern, size_t lds) {
+                             if (!kern)
+                                 return fail(ctx, USP_EINVAL,
+                                             "launch shape not built for this instance");
                              return set_lds(ctx, kern, lds);
                          });
 }
 
-// one cell-kernel pass over the batch (B.tiers set by the caller).
-// Instances that need more particle slots than the 256 x (4 | 6) shape run
-// every cell with it first; a cell that needs more is handed on, untouched,
-// to the 8-slot shape through the tier list.
+// one cell-kernel pass over the batch (B.tiers set by the caller): the first
+// shape of the chain runs every cell; a cell that needs more slots is handed
+// on, untouched, to the next shape of the chain through the tier list of
+// the shape that handed it on.
 usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int xb, int max_nb, int first,
                        int top, hipStream_t stream)
 {
@@ -352,11 +395,13 @@ usp_status launch_cell(usp_ctx* ctx, Batch B, int prec, int dim, int xb, int max
     }
     usp_status st = for_each_tier(
         prec, dim, xb, max_nb, first, top,
-        [&](int t, int lo, Shape sh, const void* kern, size_t lds) -> usp_status {
+        [&](int i, const int* chain, int n, Shape sh, const void* kern,
+            size_t lds) -> usp_status {
+            if (!kern) return fail(ctx, USP_EINVAL, "launch shape not built for this instance");
             usp_status s2 = set_lds(ctx, kern, lds);
             if (s2) return s2;
-            B.tier_in = t == lo ? nullptr : B.tiers + (size_t)(t - 1) * B.tier_stride;
-            B.tier_out = t == top ? nullptr : B.tiers + (size_t)t * B.tier_stride;
+            B.tier_in = i == 0 ? nullptr : B.tiers + (size_t)chain[i - 1] * B.tier_stride;
+            B.tier_out = i + 1 == n ? nullptr : B.tiers + (size_t)chain[i] * B.tier_stride;
             void* args[] = {(void*)&B};
             HIPCHK(ctx, hipLaunchKernel(kern, dim3(B.ncells), dim3(sh.nt), args, lds, stream));
             return USP_OK;
@@ -416,6 +461,8 @@ usp_status err_status(usp_ctx* ctx, int e)
     if (e & ERR_CAPACITY) return fail(ctx, USP_ECAPACITY, "a cell exceeded max_ppc particles");
     if (e & ERR_WINDOW)
         return fail(ctx, USP_EWINDOW, "a particle moved farther than the sort window");
+    if (e & ERR_NONFINITE)
+        return fail(ctx, USP_ENONFINITE, "a cell moment became infinite or not a number");
     return USP_OK;
 }
 
@@ -570,6 +617,11 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
     h.nb = (2 * w.Ky + 1) * h.nbx;
     if (h.nb > MAX_BINS) return fail(ctx, USP_EINVAL, "sort window larger than 256 bins");
     h.cap = (nm->max_ppc + 63) / 64 * 64;
+    {
+        double tot = 0.0;
+        for (int c = 0; c < h.ncell; ++c) tot += floor(init_n[c] * pb->vcell / nm->Np + 0.5);
+        in->mean_ppc = tot / h.ncell;
+    }
 
     const size_t ncell = (size_t)h.ncell;
     const size_t rb = h.prec == 32 ? 4 : 8;
@@ -704,6 +756,9 @@ usp_status usp_instance_free(usp_ctx* ctx, int id)
     ctx->allocated -= std::min(ctx->allocated, in->bytes);
     in->allocs.clear();
     in->fview = nullptr;
+    in->dg_mem = nullptr;
+    in->ori_mem[0] = in->ori_mem[1] = nullptr;
+    in->sorg_mem = nullptr;
     in->alive = false;
     drop_groups(ctx);
     return USP_OK;
@@ -861,6 +916,10 @@ usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps)
     std::vector<Plan> plans;
     usp_status s = make_plan(ctx, ids, n_ids, plans);
     if (s) return s;
+    for (int i = 0; i < n_ids; ++i) {
+        Instance* in = get_inst(ctx, ids[i]);
+        in->sort_ok = in->h.diag != nullptr;
+    }
     if (!ctx->graph || ctx->timing) return enqueue_all(ctx, plans, nsteps, ctx->stream);
     // graph mode: capture the whole call once, replay it afterwards
     std::vector<int> key(ids, ids + n_ids);
@@ -894,8 +953,13 @@ usp_status usp_set_shape(usp_ctx* ctx, int id, int first)
 {
     Instance* in = get_inst(ctx, id);
     if (!in) return fail(ctx, USP_ESTATE, "unknown or freed instance");
-    if (first < -1 || first > in->top())
-        return fail(ctx, USP_EINVAL, "first shape must be -1 or in [0, the instance's last shape]");
+    if (first < -1 || first >= NSHAPE || (first > in->top() && first < NSHAPE_WG))
+        return fail(ctx, USP_EINVAL,
+                    "first shape must be -1, a workgroup shape up to the instance's last, or "
+                    "a wave shape");
+    if (first == SHAPE_W6 && in->xb())
+        return fail(ctx, USP_EINVAL,
+                    "the 6-slot wave shape serves instances without open faces or the plate");
     if (first != in->first) {
         drop_groups(ctx);
         in->first = first;
@@ -1032,6 +1096,7 @@ usp_status usp_set_state(usp_ctx* ctx, int id, const int* counts, const double* 
     Instance* in = get_inst(ctx, id);
     if (!in || !counts || !parts) return fail(ctx, USP_EINVAL, "bad set_state arguments");
     const InstDev& h = in->h;
+    in->sort_ok = false;
     int ctl[CTL_N];
     usp_status s = read_ctl(ctx, in, ctl);
     if (s) return s;
@@ -1129,17 +1194,116 @@ usp_status usp_set_diag(usp_ctx* ctx, int id, int on)
 {
     Instance* in = get_inst(ctx, id);
     if (!in) return fail(ctx, USP_ESTATE, "unknown instance");
+    in->sort_ok = false;
     if (on && !in->h.diag) {
-        in->h.diag = (double*)dalloc(ctx, (size_t)in->h.ncell * NDIAG * 8);
-        if (!in->h.diag) return fail(ctx, USP_ENOMEM, "diag buffer");
-        in->allocs.push_back(in->h.diag);
-        in->bytes += (size_t)in->h.ncell * NDIAG * 8;
-        HIPCHK(ctx, hipMemsetAsync(in->h.diag, 0, (size_t)in->h.ncell * NDIAG * 8, ctx->stream));
+        if (!in->dg_mem) {
+            const size_t slots = (size_t)in->h.ncell * in->h.cap;
+            auto A = [&](size_t bytes) -> void* {
+                void* p = dalloc(ctx, bytes);
+                if (p) {
+                    in->allocs.push_back(p);
+                    in->bytes += bytes;
+                }
+                return p;
+            };
+            in->dg_mem = (double*)A((size_t)in->h.ncell * NDIAG * 8);
+            in->ori_mem[0] = (uint32_t*)A(slots * 4);
+            in->ori_mem[1] = (uint32_t*)A(slots * 4);
+            in->sorg_mem = (uint64_t*)A(slots * 8);
+            if (!in->dg_mem || !in->ori_mem[0] || !in->ori_mem[1] || !in->sorg_mem)
+                return fail(ctx, USP_ENOMEM, "diag buffers");
+        }
+        HIPCHK(ctx, hipMemsetAsync(in->dg_mem, 0, (size_t)in->h.ncell * NDIAG * 8, ctx->stream));
+        in->h.diag = in->dg_mem;
+        in->h.ori[0] = in->ori_mem[0];
+        in->h.ori[1] = in->ori_mem[1];
+        in->h.sorg = in->sorg_mem;
     } else if (!on) {
         in->h.diag = nullptr;
+        in->h.ori[0] = in->h.ori[1] = nullptr;
+        in->h.sorg = nullptr;
     }
     drop_groups(ctx);
     return upload_desc(ctx, in);
+}
+
+usp_status usp_get_sort(usp_ctx* ctx, int id, int32_t* cell_offsets, int32_t* perm)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in) return fail(ctx, USP_ESTATE, "unknown instance");
+    if (!cell_offsets) return fail(ctx, USP_EINVAL, "null cell_offsets");
+    if (!in->h.diag || !in->sort_ok)
+        return fail(ctx, USP_ESTATE, "no step has run with diagnostics on since the last load");
+    const size_t ncell = (size_t)in->h.ncell, cap = (size_t)in->h.cap;
+    std::vector<double> dg(ncell * NDIAG);
+    HIPCHK(ctx, hipMemcpyAsync(dg.data(), in->h.diag, dg.size() * 8, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<long long> pre(ncell + 1, 0);
+    cell_offsets[0] = 0;
+    for (size_t c = 0; c < ncell; ++c) {
+        cell_offsets[c + 1] = cell_offsets[c] + (int32_t)dg[c * NDIAG + D_NIN];
+        pre[c + 1] = pre[c] + (long long)dg[c * NDIAG + D_NPRE];
+    }
+    if (!perm) return USP_OK;
+    std::vector<uint64_t> so(ncell * cap);
+    HIPCHK(ctx, hipMemcpyAsync(so.data(), in->h.sorg, so.size() * 8, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (size_t c = 0; c < ncell; ++c) {
+        const int n = cell_offsets[c + 1] - cell_offsets[c];
+        for (int j = 0; j < n; ++j) {
+            const uint64_t v = so[c * cap + j];
+            const size_t src = (size_t)(v >> 32);
+            if (src >= ncell) return fail(ctx, USP_ESTATE, "sort record out of range");
+            perm[cell_offsets[c] + j] = (int32_t)(pre[src] + (long long)(v & 0xFFFFFFFFu));
+        }
+    }
+    return USP_OK;
+}
+
+usp_status usp_stats(usp_ctx* ctx, int id, usp_stats_t* out)
+{
+    Instance* in = get_inst(ctx, id);
+    if (!in) return fail(ctx, USP_ESTATE, "unknown instance");
+    if (!out) return fail(ctx, USP_EINVAL, "null stats");
+    memset(out, 0, sizeof(*out));
+    int ctl[CTL_N];
+    usp_status s = read_ctl(ctx, in, ctl);
+    if (s) return s;
+    const size_t ncell = (size_t)in->h.ncell;
+    std::vector<int> cnt(ncell);
+    HIPCHK(ctx, hipMemcpyAsync(cnt.data(), in->h.cnt, ncell * 4, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int c : cnt) out->live += c;
+    out->step = ctl[CTL_STEP];
+    out->error = ctl[CTL_ERR] ? (int)err_status(ctx, ctl[CTL_ERR]) : 0;
+    out->diag = in->h.diag != nullptr && in->sort_ok;
+    if (!out->diag) return USP_OK;
+    std::vector<double> dg(ncell * NDIAG);
+    HIPCHK(ctx, hipMemcpyAsync(dg.data(), in->h.diag, dg.size() * 8, hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (size_t c = 0; c < ncell; ++c) {
+        const double* d = dg.data() + c * NDIAG;
+        out->added[0] += (long long)d[D_N2];
+        out->added[1] += (long long)d[D_N4];
+        out->added[2] += (long long)d[D_N7];
+        out->selected += (long long)d[D_NSEL];
+        out->reassigned += (long long)d[D_NUSP];
+        out->deleted += (long long)d[D_NDEL];
+        out->entered += (long long)d[D_NINJ];
+        out->left += (long long)d[D_NGONE];
+        out->clamped += (long long)d[D_CLAMP];
+        out->es_fallback += (long long)d[D_CHOLFB];
+        const int f = (int)d[D_FLAGS];
+        out->cells_invalid += (f & F_SKIP) != 0;
+        out->mass_fail += (f & F_FAILMASS) != 0;
+        out->energy_fail += (f & F_FAILENERGY) != 0;
+        out->whole_cell += (f & F_WHOLE) != 0;
+    }
+    return USP_OK;
 }
 
 usp_status usp_get_diag(usp_ctx* ctx, int id, double* out)

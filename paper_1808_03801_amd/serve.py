@@ -108,15 +108,19 @@ class Server:
     """Admits requests by HBM footprint and advances every admitted solve in
     shared batched launches, `chunk` steps at a time."""
 
-    def __init__(self, ctx, budget: int = 2 << 30, chunk: int = 50):
+    def __init__(self, ctx, budget: int = 2 << 30, chunk: int = 50, graph: bool = True,
+                 sync_every: int = 8):
         from . import usp
         self.usp = usp
         self.ctx = ctx
         self.budget = int(budget)
         self.chunk = int(chunk)
+        self.graph = bool(graph)
+        self.sync_every = int(sync_every)
         self._queue: collections.deque = collections.deque()
         self.max_active = 0
         self.chunks = 0
+        self.syncs = 0
 
     def submit(self, req: Request) -> concurrent.futures.Future:
         fut: concurrent.futures.Future = concurrent.futures.Future()
@@ -132,12 +136,22 @@ class Server:
         """Serves everything submitted.  Requests become eligible at
         t0 + request.arrival (t0 = now by default); the loop admits eligible
         requests in order while their footprint fits, steps all active solves
-        by min(chunk, fewest remaining steps), and retires finished ones."""
+        by min(chunk, fewest remaining steps), and retires finished ones.
+
+        The host waits for the device only when a solve has finished (its
+        fields are copied out and its memory freed), when nothing is left to
+        step, or every `sync_every` chunks (to notice a failed solve early);
+        between those the chunks are queued on the stream back to back, and
+        with `graph` a chunk over an unchanged set of solves replays the HIP
+        graph captured for it.  Admitting a request creates its instance,
+        which waits for the stream."""
         t0 = clock() if t0 is None else t0
+        self.ctx.set_graph(self.graph)
         active: Dict[int, list] = {}
         used = 0
         queue = collections.deque(sorted(self._queue, key=lambda e: e[0].arrival))
         self._queue.clear()
+        pending = 0
         while queue or active:
             now = clock() - t0
             while queue and queue[0][0].arrival <= now and used + queue[0][2] <= self.budget:
@@ -152,14 +166,22 @@ class Server:
             self.max_active = max(self.max_active, len(active))
             k = min(self.chunk, min(a[2] for a in active.values()))
             self.ctx.step([a[0] for a in active.values()], k)
+            self.chunks += 1
+            pending += 1
+            finished = False
+            for a in active.values():
+                a[2] -= k
+                finished = finished or a[2] == 0
+            if not (finished or pending >= self.sync_every):
+                continue
             try:
                 self.ctx.sync()
             except self.usp.UspError:
                 pass  # a solve failed (sticky, its own): found and retired below
-            self.chunks += 1
+            self.syncs += 1
+            pending = 0
             done, failed = [], []
             for iid, a in active.items():
-                a[2] -= k
                 if a[0].status() != 0:
                     failed.append(iid)
                 elif a[2] == 0:
@@ -176,6 +198,7 @@ class Server:
                 inst.free()
                 used -= fp
                 fut.set_result(Result(req, f0, f1, t_admit, clock() - t0))
+        self.ctx.set_graph(False)
 
 
 def run_plain(ctx, reqs: List[Request], clock=time.perf_counter, chunk: int = 1000,

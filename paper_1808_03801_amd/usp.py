@@ -22,7 +22,8 @@ NF = 18
 NDIAG = 48
 
 STATUS = {0: "USP_OK", -1: "USP_EINVAL", -2: "USP_ENOMEM", -3: "USP_ECAPACITY",
-          -4: "USP_EWINDOW", -5: "USP_EDEVICE", -7: "USP_ESTATE", -8: "USP_ENOLIB"}
+          -4: "USP_EWINDOW", -5: "USP_EDEVICE", -7: "USP_ESTATE", -8: "USP_ENOLIB",
+          -9: "USP_ENONFINITE"}
 
 
 class UspError(RuntimeError):
@@ -63,6 +64,14 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 class MomentsView(C.Structure):
     _fields_ = [("ncell", C.c_int), ("nfield", C.c_int), ("data", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("live", C.c_longlong), ("step", C.c_int), ("error", C.c_int),
+                ("diag", C.c_int), ("added", C.c_longlong * 3)] + \
+               [(n, C.c_longlong) for n in ("selected", "reassigned", "deleted", "entered",
+                                            "left", "clamped", "es_fallback", "cells_invalid",
+                                            "mass_fail", "energy_fail", "whole_cell")]
 
 
 class Device(C.Structure):
@@ -111,6 +120,9 @@ def lib():
                                         C.POINTER(C.c_int)]),
             "usp_get_timing": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
             "usp_moments": (C.c_int, [vp, C.c_int, C.c_int, C.POINTER(MomentsView)]),
+            "usp_get_sort": (C.c_int, [vp, C.c_int, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32)]),
+            "usp_stats": (C.c_int, [vp, C.c_int, C.POINTER(Stats)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -126,7 +138,8 @@ def exported_symbols():
             "usp_instance_free", "usp_step", "usp_sync", "usp_instance_status", "usp_num_cells",
             "usp_num_particles", "usp_get_state", "usp_set_state", "usp_get_fields",
             "usp_set_diag", "usp_get_diag", "usp_set_block", "usp_philox", "usp_set_timing",
-            "usp_get_timing", "usp_set_graph", "usp_set_shape", "usp_get_shape", "usp_moments"]
+            "usp_get_timing", "usp_set_graph", "usp_set_shape", "usp_get_shape", "usp_moments",
+            "usp_get_sort", "usp_stats"]
 
 
 _hiplib = None
@@ -377,6 +390,26 @@ class Instance:
         out = np.zeros((self.ncell, NDIAG))
         _check(self.ctx.h, lib().usp_get_diag(self.ctx.h, self.id, _dp(out)))
         return out
+
+    def get_sort(self):
+        """usp_get_sort: (counts per cell after the last step-3 sort, place of
+        every sorted particle in the sequence before it)"""
+        off = np.zeros(self.ncell + 1, np.int32)
+        i32p = C.POINTER(C.c_int32)
+        _check(self.ctx.h, lib().usp_get_sort(self.ctx.h, self.id, off.ctypes.data_as(i32p),
+                                              None))
+        perm = np.zeros(max(int(off[-1]), 1), np.int32)
+        _check(self.ctx.h, lib().usp_get_sort(self.ctx.h, self.id, off.ctypes.data_as(i32p),
+                                              perm.ctypes.data_as(i32p)))
+        return np.diff(off).astype(np.int32), perm[:int(off[-1])].astype(np.int64)
+
+    def stats(self) -> dict:
+        """usp_stats as a dict"""
+        st = Stats()
+        _check(self.ctx.h, lib().usp_stats(self.ctx.h, self.id, C.byref(st)))
+        d = {n: getattr(st, n) for n, _ in Stats._fields_ if n != "added"}
+        d["added"] = list(st.added)
+        return d
 
     def set_shape(self, first: int):
         """first launch shape of this instance (-1: default); results unchanged"""

@@ -60,6 +60,8 @@ def test_each_result_same_alone_and_in_the_mix():
     try:
         srv, mixed = _run_server(ctx, reqs, budget=2 << 30)
         assert srv.max_active >= 4  # arrivals overlap: solves shared launches
+        # the host waited only when a solve finished (or every few chunks)
+        assert srv.syncs < srv.chunks, (srv.syncs, srv.chunks)
         alone = S.run_plain(ctx, reqs)
         by_seed = {r.request.seed: r for r in alone}
         for m in mixed:
