@@ -31,6 +31,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+
+def progress(msg):
+    """one line on stderr as each phase of the run ends"""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 PEAK_HBM_GBS = 8000.0
 # algorithmic bytes per particle-step: one read and one write of the particle
 # record (FP32: y, cx, cy, cz, w = 20 B each way in 1-D; x as well in 2-D)
@@ -285,9 +291,11 @@ def serving(n, steps, budget):
     srv.run(t0=t0)
     wall_b = time.perf_counter() - t0
     batched = [f.result() for f in futs]
+    progress(f"serving: {n} requests batched in {wall_b:.1f} s")
     t0 = time.perf_counter()
     plain = S.run_plain(ctx, reqs, t0=t0)
     wall_p = time.perf_counter() - t0
+    progress(f"serving: {n} requests one at a time in {wall_p:.1f} s")
     same = all(
         np.array_equal(b.fields, p.fields)
         for b, p in zip(sorted(batched, key=lambda r: r.request.seed),
@@ -337,9 +345,14 @@ def main():
 
     # the oracle first, in forked processes, before anything touches the GPU
     cpu = None if args.no_cpu else cpu_baseline(args.workload, args.cpu_steps)
+    if cpu is not None:
+        progress("cpu baseline: %.3g particle-updates/s on one core, %.3g on %d"
+                 % (cpu["value"], cpu["all_cores"]["value"], cpu["all_cores"]["cores"]))
 
     head = measure(args.workload, args.steps, args.warmup, args.chunk, not args.no_graph,
                    not args.no_tune)
+    progress("%s: %.4g particle-updates/s, %.3f ms per step"
+             % (args.workload, head["value"], head["ms_per_step"]))
     line = {
         "metric": "particle-updates/s",
         "value": head["value"],
@@ -361,6 +374,8 @@ def main():
     if args.second:
         sec = measure(args.second, 400, 40, args.chunk, not args.no_graph, not args.no_tune)
         line[args.second] = sec
+        progress("%s: %.4g particle-updates/s, %.3f ms per step"
+                 % (args.second, sec["value"], sec["ms_per_step"]))
     if args.serve > 0:
         lo, hi = (int(v) for v in args.serve_steps.split(","))
         line["serving"] = serving(args.serve, (lo, hi), int(args.serve_budget * (1 << 30)))

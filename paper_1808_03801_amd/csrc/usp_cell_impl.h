@@ -874,9 +874,11 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
         // that relaxes budgets three batches whether or not it also moves:
         // which shape relaxes a cell then does not depend on how a run is
         // split into calls (wave and workgroup shapes add in different
-        // orders).
-        const int nbat = (mode & MODE_RELAX) ? 3 : 1;
-        const double sp = fmax(L.pre[26], 0.0);
+        // orders).  A pass that only takes moments adds nothing and reads no
+        // previous moments (after a state is created or loaded there are
+        // none).
+        const int nbat = (mode & MODE_RELAX) ? 3 : ((mode & MODE_MOVE) ? 1 : 0);
+        const double sp = nbat > 0 ? fmax(L.pre[26], 0.0) : 0.0;
         const double est = n0 + nbat * (1.1 * sp / I.r_p + 8.0);
         if (n0 > CAP || est > (double)CAP) return defer(1);
     }

@@ -711,6 +711,13 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
     }
     HIPCHK(ctx, hipMemsetAsync(h.ctl, 0, CTL_N * 4, ctx->stream));
     HIPCHK(ctx, hipMemsetAsync(h.far_n, 0, 2 * sizeof(int), ctx->stream));
+    // per-cell records start defined: nothing of a previous user of this
+    // memory can reach a kernel
+    HIPCHK(ctx, hipMemsetAsync(h.mom, 0, NMOM * ncell * 8, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(h.raw, 0, NMOM * ncell * 8, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(h.pcur, 0, ncell * 8, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(h.pprev, 0, ncell * 8, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(h.cnt, 0, ncell * 4, ctx->stream));
     int base[2] = {0, h.ncell};
     HIPCHK(ctx, hipMemcpyAsync(in->dbase, base, sizeof(base), hipMemcpyHostToDevice, ctx->stream));
     if ((s = upload_desc(ctx, in))) return s;
