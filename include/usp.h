@@ -190,8 +190,9 @@ usp_status usp_instance_free(usp_ctx* ctx, int id);
  * dimension, launch shape) share every kernel launch (batched); flavours run
  * side by side on internal streams forked from and joined back to the
  * context's stream.  Asynchronous: returns once the work is enqueued.
- * Errors: USP_EINVAL (no ids), USP_ESTATE (unknown, freed or failed id),
- * USP_ENOMEM (batch tables), USP_EDEVICE (HIP launch or capture failure). */
+ * Errors: USP_EINVAL (no ids, or an id listed twice), USP_ESTATE (unknown,
+ * freed or failed id), USP_ENOMEM (batch tables), USP_EDEVICE (HIP launch or
+ * capture failure). */
 usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps);
 
 /* Waits for the stream; reports the first sticky instance error, if any. */
@@ -285,18 +286,26 @@ usp_status usp_stats(usp_ctx* ctx, int id, usp_stats_t* out);
  * is the only accepted value; others return USP_EINVAL. */
 usp_status usp_set_block(usp_ctx* ctx, int threads);
 
-/* Launch shapes of the cell kernel.  Shape s (0 <= s < nshape) holds a cell
+/* Launch shapes of the cell kernel.  Workgroup shapes s = 0..4 hold a cell
  * in 256 threads x {1, 2, 4, 4|6, 8}[s] particle slots per thread (4|6: the
- * cell reruns with 6 slots when 4 are too few).  An instance's last shape is
- * the smallest that holds max_ppc; its first shape (default: the last, or
- * shape 3 when the last is 4) runs every cell, and cells that need more
- * slots are handed on, before anything of them is written, to the following
- * shapes up to the last.  Every shape computes bit-identical results (all
- * use 256 threads and the same reduction order), so the choice only changes
- * speed: usp_set_shape is the knob an autotuner turns.  first = -1 restores
- * the default.  Errors: USP_ESTATE (unknown id), USP_EINVAL (first outside
- * [-1, last]).  usp_get_shape returns the first and last shape in use and
- * the number of shapes. */
+ * cell reruns with 6 slots when 4 are too few); wave shapes 5 and 6 hold a
+ * cell in one 64-lane wave with 4 and 6 slots per lane (shape 6 only for
+ * instances without open faces or the plate).  An instance's last shape is
+ * the smallest workgroup shape that holds max_ppc.  Its first shape runs
+ * every cell; cells that need more slots are handed on, before anything of
+ * them is written, to the workgroup shapes with more slots, up to the last.
+ * The default first shape is a wave shape when the initial particles per
+ * cell leave room for the added particles in one wave (4 or 6 slots), else
+ * the smaller of the last shape and shape 3.  Shapes of one family
+ * (workgroup or wave) reduce in the same order and give bit-identical
+ * results; the two families reduce in different orders, so moving an
+ * instance to the other family changes the last bits of its moments (every
+ * shape passes the same parity bar).  usp_set_shape is the knob an
+ * autotuner turns; first = -1 restores the default.  Errors: USP_ESTATE
+ * (unknown id), USP_EINVAL (a workgroup shape above the last, a value
+ * outside [-1, nshape), or shape 6 for an instance with open faces or the
+ * plate).  usp_get_shape returns the first and last shape in use and the
+ * number of shapes (7). */
 usp_status usp_set_shape(usp_ctx* ctx, int id, int first);
 usp_status usp_get_shape(usp_ctx* ctx, int id, int* first, int* last, int* nshape);
 

@@ -795,8 +795,11 @@ struct Plan {
 // (all of it before any launch: a graph capture may follow)
 usp_status make_plan(usp_ctx* ctx, const int* ids, int n_ids, std::vector<Plan>& plans)
 {
-    for (int i = 0; i < n_ids; ++i)
+    std::vector<char> seen(ctx->inst.size(), 0);
+    for (int i = 0; i < n_ids; ++i) {
         if (!get_inst(ctx, ids[i])) return fail(ctx, USP_ESTATE, "unknown or freed instance in step");
+        if (seen[ids[i]]++) return fail(ctx, USP_EINVAL, "an instance listed twice in one step");
+    }
     // flavour = (precision, dimension, boundary set, first shape, last
     // shape); the map keeps the groups in a fixed order
     std::map<std::vector<int>, std::vector<int>> flavours;

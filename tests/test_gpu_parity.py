@@ -289,6 +289,22 @@ def test_mode_switches_outside_their_values_are_refused(ctx):
 
 
 @pytest.mark.gpu
+def test_an_instance_listed_twice_in_one_step_is_refused(ctx):
+    """two workgroups on the same cells would race: refused before any launch"""
+    usp = _gpu()
+    x = ctx.add(P.couette_1d(ncell=20, ppc=50, seed=1))
+    try:
+        with pytest.raises(usp.UspError) as e:
+            ctx.step([x, x], 2)
+        assert e.value.status == -1
+        ctx.step([x], 2)
+        ctx.sync()
+        assert x.get_state().step == 2
+    finally:
+        x.free()
+
+
+@pytest.mark.gpu
 def test_cells_handed_to_larger_shapes():
     """cells whose particles outgrow the 256 x 4 shape's slots finish in a
     larger one (parity with the oracle is checked by the single-step test of
