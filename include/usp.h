@@ -195,6 +195,24 @@ usp_status usp_instance_free(usp_ctx* ctx, int id);
  * capture failure). */
 usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps);
 
+/* usp_step for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops that must not call hipMalloc, harnesses that
+ * forbid it.  Same arguments and the same results, bit for bit, as usp_step;
+ * the instances themselves are created beforehand (usp_instance_init
+ * allocates).  The call allocates nothing: the batch descriptor table, the
+ * per-group base offsets and the shape-tier lists live in a static device
+ * array of about 15 MiB that the library holds on each device it runs on
+ * until the process ends.  Flavour groups run one after another on the
+ * context's stream (no internal streams, no graph, no timing events; kernel
+ * timing is not recorded for these calls).  Limits: at most 1024 instances
+ * and 524288 cells in one call, else USP_EINVAL before anything is enqueued.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (from several contexts or host threads, or on streams not
+ * ordered with each other) race and must not be made.  Errors: as usp_step,
+ * plus USP_EINVAL for the limits and USP_EDEVICE when the array's address
+ * could not be taken at usp_create. */
+usp_status usp_step_noalloc(usp_ctx* ctx, const int* ids, int n_ids, int nsteps);
+
 /* Waits for the stream; reports the first sticky instance error, if any. */
 usp_status usp_sync(usp_ctx* ctx);
 /* Sticky device error status of one instance (synchronises). */

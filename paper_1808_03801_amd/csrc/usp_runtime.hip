@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -72,6 +73,65 @@ struct Instance {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Static scratch of usp_step_noalloc: one call's batch descriptor table, the
+// instance base offsets of each launch group and the shape-tier lists, in a
+// device array of the code object (one copy per device, held until the
+// process ends).  In host code `scratch` names a host-side stand-in, not the
+// device array: its device address is taken once per device with
+// hipGetSymbolAddress (usp_create) and only that address reaches kernels.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int NA_MAX_INST = 1024;       // instances per call
+constexpr int NA_MAX_CELLS = 1 << 19;   // cells per call, all instances
+constexpr int NA_MAX_DEV = 64;
+constexpr size_t na_round(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t NA_TABLE_BYTES = na_round(sizeof(InstDev) * NA_MAX_INST);
+// a group of m instances takes m + 1 base entries: at most 2 x NA_MAX_INST
+constexpr size_t NA_BASE_BYTES = na_round(sizeof(int) * 2 * NA_MAX_INST);
+constexpr size_t NA_TIER_BYTES = na_round(sizeof(int) * NSHAPE * (size_t)(1 + NA_MAX_CELLS));
+constexpr size_t NA_BYTES = NA_TABLE_BYTES + NA_BASE_BYTES + NA_TIER_BYTES;
+static_assert(sizeof(InstDev) % 4 == 0, "descriptors are copied as 32-bit words");
+
+std::mutex na_mu;
+void* na_ptr[NA_MAX_DEV];  // device address of `scratch` per device
+
+// copies instance descriptors into a batch table: block i copies src[i]
+constexpr int NA_PACK = 64;
+struct DescPack {
+    const InstDev* src[NA_PACK];
+    int n;
+};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+__global__ void na_copy_desc(DescPack pk, InstDev* dst)
+{
+    const int i = blockIdx.x;
+    if (i >= pk.n) return;
+    const uint32_t* s = (const uint32_t*)pk.src[i];
+    uint32_t* d = (uint32_t*)(dst + i);
+    for (int w = threadIdx.x; w < (int)(sizeof(InstDev) / 4); w += blockDim.x) d[w] = s[w];
+}
+
+// base offsets of a batch table (base[0] = 0, base[i + 1] = base[i] + ncell
+// of instance i) and cleared counts of the group's tier lists
+__global__ void na_base_tiers(const InstDev* tbl, int n, int* base, int* tiers, int stride)
+{
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        base[0] = 0;
+        for (int i = 0; i < n; ++i) {
+            acc += tbl[i].ncell;
+            base[i + 1] = acc;
+        }
+    }
+    if (threadIdx.x < NSHAPE) tiers[(size_t)threadIdx.x * stride] = 0;
+}
+}  // namespace
+
 struct usp_ctx {
     usp_device dev;
     hipStream_t stream = nullptr;
@@ -103,6 +163,8 @@ struct usp_ctx {
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> join;
     hipEvent_t fork = nullptr;
+    // device address of the static scratch array (usp_step_noalloc)
+    void* scratch = nullptr;
     // graph replay of whole usp_step calls, keyed by (instance ids, steps)
     bool graph = false;
     hipStream_t cap = nullptr;
@@ -507,6 +569,24 @@ usp_status usp_create(const usp_device* dev, usp_ctx** out)
     if (hipSetDevice(ctx->dev.device) != hipSuccess) {
         delete ctx;
         return USP_EDEVICE;
+    }
+    if (ctx->dev.device < 0 || ctx->dev.device >= NA_MAX_DEV) {
+        delete ctx;
+        return USP_EINVAL;
+    }
+    {
+        // the scratch array's address on this device (the device is current)
+        std::lock_guard<std::mutex> lock(na_mu);
+        void*& p = na_ptr[ctx->dev.device];
+        if (!p) {
+            void* q = nullptr;
+            if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) {
+                delete ctx;
+                return USP_EDEVICE;
+            }
+            p = q;
+        }
+        ctx->scratch = p;
     }
     *out = ctx;
     return USP_OK;
@@ -956,6 +1036,96 @@ usp_status usp_step(usp_ctx* ctx, const int* ids, int n_ids, int nsteps)
         it = ctx->graphs.emplace(key, exec).first;
     }
     HIPCHK(ctx, hipGraphLaunch(it->second, ctx->stream));
+    return USP_OK;
+}
+
+usp_status usp_step_noalloc(usp_ctx* ctx, const int* ids, int n_ids, int nsteps)
+{
+    if (!ctx || !ids || n_ids <= 0) return fail(ctx, USP_EINVAL, "no instances");
+    if (n_ids > NA_MAX_INST)
+        return fail(ctx, USP_EINVAL, "usp_step_noalloc: more than 1024 instances in one call");
+    if (!ctx->scratch) return fail(ctx, USP_EDEVICE, "usp_step_noalloc: no scratch address");
+    // flavour of each instance; duplicates found after sorting by (flavour, id)
+    long long key[NA_MAX_INST];
+    long long cells = 0;
+    for (int i = 0; i < n_ids; ++i) {
+        Instance* in = get_inst(ctx, ids[i]);
+        if (!in) return fail(ctx, USP_ESTATE, "unknown or freed instance in step");
+        cells += in->h.ncell;
+        const long long fl = ((((long long)(in->h.prec == 64) * 2 + (in->h.dim - 1)) * 2 +
+                               in->xb()) * NSHAPE + in->first_shape()) * NSHAPE + in->top();
+        key[i] = (fl << 32) | (long long)(uint32_t)ids[i];
+    }
+    if (cells > NA_MAX_CELLS)
+        return fail(ctx, USP_EINVAL,
+                    "usp_step_noalloc: more than 524288 cells in one call (" +
+                        std::to_string(cells) + ")");
+    std::sort(key, key + n_ids);
+    for (int i = 1; i < n_ids; ++i)
+        if (key[i] == key[i - 1])
+            return fail(ctx, USP_EINVAL, "an instance listed twice in one step");
+    if (nsteps <= 0) return USP_OK;
+    InstDev* table = (InstDev*)ctx->scratch;
+    int* base_all = (int*)((char*)ctx->scratch + NA_TABLE_BYTES);
+    int* tiers = (int*)((char*)ctx->scratch + NA_TABLE_BYTES + NA_BASE_BYTES);
+    // no timing events (they would be created here)
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    auto run = [&]() -> usp_status {
+        // one group per flavour, one after another on the context's stream;
+        // the groups share the tier lists
+        int g0 = 0, ngroup = 0;
+        while (g0 < n_ids) {
+            int g1 = g0;
+            while (g1 < n_ids && (key[g1] >> 32) == (key[g0] >> 32)) ++g1;
+            Instance* f = get_inst(ctx, (int)(uint32_t)key[g0]);
+            int ncells = 0, max_nb = 0;
+            for (int k = g0; k < g1; ++k) {
+                const Instance* in = get_inst(ctx, (int)(uint32_t)key[k]);
+                ncells += in->h.ncell;
+                max_nb = std::max(max_nb, in->h.nb);
+            }
+            InstDev* tbl = table + g0;
+            int* base = base_all + g0 + ngroup;
+            for (int k = g0; k < g1; k += NA_PACK) {
+                DescPack pk;
+                pk.n = std::min(NA_PACK, g1 - k);
+                for (int j = 0; j < pk.n; ++j) pk.src[j] = get_inst(ctx, (int)(uint32_t)key[k + j])->d;
+                hipLaunchKernelGGL(na_copy_desc, dim3(pk.n), dim3(64), 0, ctx->stream, pk,
+                                   tbl + (k - g0));
+                HIPCHK(ctx, hipGetLastError());
+            }
+            hipLaunchKernelGGL(na_base_tiers, dim3(1), dim3(64), 0, ctx->stream, tbl, g1 - g0,
+                               base, tiers, 1 + ncells);
+            HIPCHK(ctx, hipGetLastError());
+            Plan P;
+            P.B.inst = tbl;
+            P.B.base = base;
+            P.B.ninst = g1 - g0;
+            P.B.ncells = ncells;
+            P.B.tiers = tiers;
+            P.B.tier_stride = 1 + ncells;
+            P.prec = f->h.prec;
+            P.dim = f->h.dim;
+            P.xb = f->xb();
+            P.max_nb = max_nb;
+            P.first = f->first_shape();
+            P.top = f->top();
+            usp_status st = prepare_cell(ctx, P.prec, P.dim, P.xb, max_nb, P.first, P.top);
+            if (st) return st;
+            if ((st = enqueue_group(ctx, P, nsteps, ctx->stream))) return st;
+            g0 = g1;
+            ++ngroup;
+        }
+        return USP_OK;
+    };
+    const usp_status s = run();
+    ctx->timing = timing;
+    if (s) return s;
+    for (int i = 0; i < n_ids; ++i) {
+        Instance* in = get_inst(ctx, ids[i]);
+        in->sort_ok = in->h.diag != nullptr;
+    }
     return USP_OK;
 }
 

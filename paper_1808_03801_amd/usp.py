@@ -102,6 +102,7 @@ def lib():
                                             C.POINTER(Numerics), dp, dp, dp, ip]),
             "usp_instance_free": (C.c_int, [vp, C.c_int]),
             "usp_step": (C.c_int, [vp, ip, C.c_int, C.c_int]),
+            "usp_step_noalloc": (C.c_int, [vp, ip, C.c_int, C.c_int]),
             "usp_sync": (C.c_int, [vp]),
             "usp_instance_status": (C.c_int, [vp, C.c_int]),
             "usp_num_cells": (C.c_int, [vp, C.c_int, ip]),
@@ -139,7 +140,7 @@ def exported_symbols():
             "usp_num_particles", "usp_get_state", "usp_set_state", "usp_get_fields",
             "usp_set_diag", "usp_get_diag", "usp_set_block", "usp_philox", "usp_set_timing",
             "usp_get_timing", "usp_set_graph", "usp_set_shape", "usp_get_shape", "usp_moments",
-            "usp_get_sort", "usp_stats"]
+            "usp_get_sort", "usp_stats", "usp_step_noalloc"]
 
 
 _hiplib = None
@@ -287,6 +288,11 @@ class Context:
     def step(self, instances, nsteps: int = 1):
         ids = np.array([i.id for i in instances], dtype=np.int32)
         _check(self.h, lib().usp_step(self.h, _ip(ids), len(ids), int(nsteps)))
+
+    def step_noalloc(self, instances, nsteps: int = 1):
+        """usp_step without device allocation (static scratch; see the header)"""
+        ids = np.array([i.id for i in instances], dtype=np.int32)
+        _check(self.h, lib().usp_step_noalloc(self.h, _ip(ids), len(ids), int(nsteps)))
 
     def sync(self):
         _check(self.h, lib().usp_sync(self.h))
