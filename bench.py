@@ -4,18 +4,19 @@ Headline workload (the largest single-GPU configuration): the flow through a
 slit of Section 4.5, 400 x 200 cells, 100 particles per cell on average (8 M
 per instance), pressure ratio 2, hard spheres, FP32 particle state with FP64
 cell moments, at Kn = 0.01 and Kn = 0.1 -- both instances advanced together
-in the same kernel launches (16.5 M live particles).  Second record: the 1-D
-thermal Couette flow and Sod tube of the continuum workload (1000 cells x 500
-particles per cell each, Kn = 1e-3, dt = 5 tau_c).  Serving: the request mix
-of Couette / Poiseuille / Sod solves.  Synthetic inputs (seeded Philox initial
-states); no external data.
+in the same kernel launches (16.5 M live particles).  Further records: the
+1-D thermal Couette flow and Sod tube of the continuum workload (1000 cells x
+500 particles per cell each, Kn = 1e-3, dt = 5 tau_c) and the lid-driven
+cavity of Section 4.4 (128 x 128 cells, 200 particles per cell, Kn = 1e-3,
+1e-2 and 0.1 batched).  Serving: the request mix of Couette / Poiseuille / Sod
+solves.  Synthetic inputs (seeded Philox initial states); no external data.
 
 A "step" is one full time step (Table 2 steps 2-8) of every instance of the
 workload.  value = live particles (weighted included) x steps / wall time of
 the timed region, with all state resident in HBM.
 
-Prints one JSON line (see the "roofline", "valu_issue", "c2", "serving" and
-"cpu_baseline" members).
+Prints one JSON line (see the "roofline", "valu_issue", "c2", "c3", "serving"
+and "cpu_baseline" members).
 """
 import argparse
 import hashlib
@@ -52,9 +53,10 @@ BYTES_PER_CELL_STEP = 6 * 13 * 8 + 8 + 4
 PROFILES = {
     "c5": os.path.join(ROOT, "profiles", "cell_kernel_slit_2d_c5.md"),
     "c2": os.path.join(ROOT, "profiles", "cell_kernel_thermal_couette_sod_1d.md"),
+    "c3": os.path.join(ROOT, "profiles", "cell_kernel_cavity_2d_c3.md"),
 }
 KERNEL_SOURCES = ("usp_cell_impl.h", "usp_device.h", "usp_common.h", "usp_cell_f32_1d.hip",
-                  "usp_cell_f32_2d_xb.hip", "usp_kernels.hip")
+                  "usp_cell_f32_2d.hip", "usp_cell_f32_2d_xb.hip", "usp_kernels.hip")
 
 # wave64 VALU instructions the chip can issue per second: 256 CUs x 4 SIMDs,
 # one wave64 instruction per SIMD every 4 cycles (16 lanes), 2.4 GHz
@@ -108,10 +110,22 @@ def workload_c2():
     return [tc, sod]
 
 
+def workload_c3():
+    """the lid-driven cavity of Section 4.4 at the three Knudsen numbers (one
+    instance each, batched)"""
+    from paper_1808_03801_amd import problems as P
+    return [P.cavity_2d(Kn=kn, n=128, ppc=200, seed=11 + i)
+            for i, kn in enumerate((1e-3, 1e-2, 0.1))]
+
+
 WORKLOADS = {
     "c5": (workload_c5, "flow through a slit (2-D, Section 4.5), 400 x 200 cells, 100 "
                         "particles/cell mean (8 M per instance), pressure ratio 2, hard spheres, "
                         "Kn = 0.01 and Kn = 0.1 batched per launch, dt = 0.3 dx / mean speed, "
+                        "FP32 particles, FP64 cell moments"),
+    "c3": (workload_c3, "lid-driven cavity (2-D, Section 4.4), 128 x 128 cells, 200 "
+                        "particles/cell (3.3 M per instance), lid 50 m/s, diffuse walls, "
+                        "Kn = 1e-3, 1e-2 and 0.1 batched per launch, dt = 0.3 dx / mean speed, "
                         "FP32 particles, FP64 cell moments"),
     "c2": (workload_c2, "thermal Couette + Sod tube (1-D), 1000 cells x 500 particles/cell "
                         "each, Kn=1e-3, dt=5 tau_c, FP32 particles, FP64 cell moments, both "
@@ -318,8 +332,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--chunk", type=int, default=20, help="steps per library call")
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
-    ap.add_argument("--second", default="c2",
-                    help="workload of the second record ('' to skip)")
+    ap.add_argument("--also", default="c2,c3",
+                    help="workloads of the further records, comma-separated ('' for none)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true",
@@ -371,11 +385,14 @@ def main():
         "roofline": head["roofline"],
         "valu_issue": head["valu_issue"],
     }
-    if args.second:
-        sec = measure(args.second, 400, 40, args.chunk, not args.no_graph, not args.no_tune)
-        line[args.second] = sec
+    for name in [w for w in args.also.split(",") if w]:
+        if name not in WORKLOADS:
+            raise SystemExit("unknown workload %r" % name)
+        steps = 400 if name == "c2" else 100
+        sec = measure(name, steps, steps // 10, args.chunk, not args.no_graph, not args.no_tune)
+        line[name] = sec
         progress("%s: %.4g particle-updates/s, %.3f ms per step"
-                 % (args.second, sec["value"], sec["ms_per_step"]))
+                 % (name, sec["value"], sec["ms_per_step"]))
     if args.serve > 0:
         lo, hi = (int(v) for v in args.serve_steps.split(","))
         line["serving"] = serving(args.serve, (lo, hi), int(args.serve_budget * (1 << 30)))

@@ -1597,11 +1597,15 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
 // more cells in flight pay for some register spills: 4 for the 1-, 2- and
 // 4-slot workgroup shapes (128 VGPRs), 3 for 4|6 (168 VGPRs); measured 9 %
 // (C2 pair) to 32 % (cavity) faster than without spills at 3 and 2
-// workgroups per CU.  One-wave cells: 4 waves per SIMD, 16 cells per CU.
+// workgroups per CU.  One-wave cells: 3 waves per SIMD with 4 slots per lane
+// (168 VGPRs, 12 cells per CU) and 2 with 6 (256 VGPRs, 8 cells per CU):
+// at 4 waves the 4-slot kernel spilled 400 B per lane (the slit pair 15 %
+// slower) and the 6-slot kernel more (the cavity triple 20 % slower).
 template <int NT, int PPT, int PPT2>
 constexpr int cell_waves_per_simd()
 {
-    return NT == 64 ? 4 : (PPT2 > 0 ? 3 : (PPT <= 4 ? 4 : 1));
+    if (NT == 64) return PPT <= 4 ? 3 : 2;
+    return PPT2 > 0 ? 3 : (PPT <= 4 ? 4 : 1);
 }
 
 template <typename real, int DIM, int NT, int PPT, int PPT2, bool XB>
