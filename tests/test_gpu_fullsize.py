@@ -72,10 +72,18 @@ def test_thermal_couette_and_sod_full_size_fused_pass():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("kn", [1e-3, 0.1])
+@pytest.mark.parametrize("kn", [1e-3, 1e-2, 0.1])
 def test_cavity_full_size(kn):
     """128 x 128 cells x 200 particles/cell (3.3 M), FP32"""
     _parity([P.cavity_2d(Kn=kn, seed=21)])
+
+
+@pytest.mark.gpu
+def test_cavity_three_knudsen_full_size_fused_pass():
+    """the cavity at Kn = 1e-3, 1e-2 and 0.1 batched in one launch over two
+    steps in one call (the fused pass, one-wave cells: the benchmark's
+    cavity workload)"""
+    _parity(bench.workload_c3(), steps=2)
 
 
 @pytest.mark.gpu
@@ -84,6 +92,13 @@ def test_slit_full_size(kn):
     """400 x 200 cells x 100 particles/cell (8 M), FP32, pressure ratio 2:
     open faces on three sides, the plate, the symmetry plane"""
     _parity([P.slit_2d(Kn=kn, seed=23)])
+
+
+@pytest.mark.gpu
+def test_slit_pair_full_size_fused_pass():
+    """the slit at both Knudsen numbers batched, two steps in one call: the
+    fused pass of the headline benchmark workload"""
+    _parity(bench.workload_c5(), steps=2)
 
 
 @pytest.mark.gpu
