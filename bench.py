@@ -278,12 +278,22 @@ def measure(name, steps, warmup, chunk, graph, tune):
     }
     r = out["roofline"]
     v = out["valu_issue"]
-    r["limiter"] = ("VALU issue of the per-cell phases (%s of issue peak) rather than HBM "
-                    "(%.1f %% of peak algorithmic, %s measured)"
-                    % ("unmeasured" if v is None else "%.0f %%" % (100 * v["frac"]),
+    # the regime, from the measured fractions: the larger of VALU issue and
+    # measured HBM traffic (the algorithmic bytes are the roofline's floor)
+    vf = None if v is None else v["frac"]
+    tf = r["traffic_frac"]
+    if vf is not None and (tf is None or vf >= tf):
+        regime = "VALU issue and per-cell latency"
+    elif tf is not None:
+        regime = "HBM traffic"
+    else:
+        regime = "unmeasured"
+    r["regime"] = regime
+    r["limiter"] = ("%s: VALU issue %s of peak, HBM %.1f %% of peak at the algorithmic "
+                    "bytes and %s at the measured traffic"
+                    % (regime, "unmeasured" if vf is None else "%.0f %%" % (100 * vf),
                        100 * r["frac"],
-                       "unmeasured" if r["traffic_frac"] is None
-                       else "%.1f %%" % (100 * r["traffic_frac"])))
+                       "unmeasured" if tf is None else "%.1f %%" % (100 * tf)))
     for i in inst:
         i.free()
     ctx.close()
