@@ -1,7 +1,8 @@
 // gfx950 auxiliary kernels of the USP-ESBGK step (arXiv 1808.03801): the
 // initial state (Table 2 step 1), P_ne of every cell from its own and its
 // neighbours' moments (Eq. 16-18, 36), per-instance control words, the field
-// record for output, and a Philox check.  The cell kernel is in usp_cell.hip.
+// record for output, and a Philox check.  The cell kernel is in usp_cell_impl.h
+// (instantiated by the usp_cell_f{32,64}_{1,2}d[_xb].hip files).
 #include "usp_device.h"
 
 namespace usp {
