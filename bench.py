@@ -63,11 +63,19 @@ KERNEL_SOURCES = ("usp_cell_impl.h", "usp_device.h", "usp_common.h", "usp_cell_f
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
+def _code_only(text):
+    """source text without comments and blank lines (a comment cannot change
+    a kernel, so it does not retire a measurement)"""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1808_03801_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1808_03801_amd", "csrc", f)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
