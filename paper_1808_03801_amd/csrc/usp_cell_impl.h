@@ -294,6 +294,27 @@ __device__ void moments_r(const Parts<real, DIM, PPT>& P, const Lds& L, int tid,
 // positions [a, a + n) with logical slots [ls, ls + n).  Sampling in double
 // precision, stored once rounded.  Optional zero-moment projection.
 // ---------------------------------------------------------------------------
+// Eq. 25 count of an added batch: S0 min(1, x) / r_p rounded
+// stochastically (floor plus a Bernoulli draw of the fraction); 0 for an
+// invalid cell or P_ne = 0.  `marg` (optional) keeps the smallest distance
+// of the draw from its threshold.
+__device__ __forceinline__ int spawn_count(const InstDev& I, int batch, int cell, uint32_t step,
+                                           const CellF& f, double pne, double* marg)
+{
+    if (!f.valid || !(pne > 0.0) || !(f.x > 0.0)) return 0;
+    const double m1 = f.x < 1.0 ? f.x : 1.0;
+    // held in [0, 1e6] before it becomes an int: a blown-up cell's S0 must
+    // reach the capacity tests, not overflow the int (a count of 2^31 wraps
+    // the capacity sums negative)
+    const double v = fmin(fmax(f.S0 * m1 / I.r_p, 0.0), 1.0e6);
+    uint32_t r[4];
+    draw(I, step, PUR_SPAWN_CNT, (uint32_t)batch, (uint32_t)cell, 0u, r);
+    const double u = uni_d(r[0], I.prec);
+    const double fl = floor(v);
+    if (marg) *marg = fmin(*marg, fabs(u - (v - fl)));
+    return (int)fl + (u < v - fl ? 1 : 0);
+}
+
 template <int NT, typename real, int DIM, int PPT>
 __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L, int batch,
                        int cell, int ix, int iy, uint32_t step, const CellF& f, double pne, int a,
@@ -301,16 +322,7 @@ __device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
 {
     if (!f.valid || !(pne > 0.0) || !(f.x > 0.0)) return 0;
     const double m1 = f.x < 1.0 ? f.x : 1.0;
-    // Eq. 25 count, held in [0, 1e6] before it becomes an int: a blown-up
-    // cell's S0 must reach the capacity test below, not overflow the int
-    // (a count of 2^31 wraps the capacity sums negative)
-    const double v = fmin(fmax(f.S0 * m1 / I.r_p, 0.0), 1.0e6);
-    uint32_t r[4];
-    draw(I, step, PUR_SPAWN_CNT, (uint32_t)batch, (uint32_t)cell, 0u, r);
-    const double u = uni_d(r[0], I.prec);
-    const double fl = floor(v);
-    int na = (int)fl + (u < v - fl ? 1 : 0);
-    if (marg) *marg = fmin(*marg, fabs(u - (v - fl)));
+    int na = spawn_count(I, batch, cell, step, f, pne, marg);
     if (ls + na > I.max_ppc || a + na > PPT * NT) {
         // too many for this shape's slots only: a larger shape redoes the cell
         if (can_defer && ls + na <= I.max_ppc) return -1;
@@ -869,17 +881,28 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
     int n0 = gs.n0;
     errbits |= gs.err;
     if (can_defer && n0 <= I.max_ppc) {
-        // particles added in this launch: S0 / r_p per batch (S0 of the
-        // cell's previous moments standing in for the current one).  A pass
-        // that relaxes budgets three batches whether or not it also moves:
-        // which shape relaxes a cell then does not depend on how a run is
-        // split into calls (wave and workgroup shapes add in different
-        // orders).  A pass that only takes moments adds nothing and reads no
-        // previous moments (after a state is created or loaded there are
-        // none).
+        // an early hand-on, before any work on the cell: the batches this
+        // pass will add, about S0 / r_p each (S0 of the cell's previous
+        // moments standing in for the current one).  A pass that relaxes
+        // budgets three batches (steps 4, 7 and the next step 2) whether or
+        // not it also moves.  The exact tests come later (steps 4 and 7 as
+        // their batches are drawn; step 2 and the entering particles of the
+        // next move in every relaxing pass, the fused one as it draws them
+        // and the one that only relaxes at its end), so which shape relaxes
+        // a cell does not depend on how a run is split into calls (wave and
+        // workgroup shapes add in different orders).  The margin weighs a
+        // late hand-on, which wastes the relaxation done so far, against an
+        // early one: in a one-wave cell the first is cheap and the second
+        // sends the cell to a four-wave shape (S0 / r_p + 1 per batch: on
+        // the slit 13 % faster than with 1.1 S0 / r_p + 8); in a workgroup
+        // cell a late hand-on wastes a workgroup's relaxation
+        // (1.05 S0 / r_p + 3).  A pass that only takes moments adds nothing
+        // and reads no previous moments (after a state is created or loaded
+        // there are none).
         const int nbat = (mode & MODE_RELAX) ? 3 : ((mode & MODE_MOVE) ? 1 : 0);
         const double sp = nbat > 0 ? fmax(L.pre[26], 0.0) : 0.0;
-        const double est = n0 + nbat * (1.1 * sp / I.r_p + 8.0);
+        const double per = NT == 64 ? sp / I.r_p + 1.0 : 1.05 * sp / I.r_p + 3.0;
+        const double est = n0 + nbat * per;
         if (n0 > CAP || est > (double)CAP) return defer(1);
     }
     if (n0 > I.max_ppc || n0 > CAP) {
@@ -1553,6 +1576,41 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             }
         }
     } else {
+        if ((mode & MODE_RELAX) && can_defer) {
+            // a relaxing pass that does not move tests the next move's
+            // additions as the fused pass does (step 2 of the next time
+            // level, then the entering particles): a cell that the fused
+            // pass would hand on here is handed on here too
+            const uint32_t mstep = step + 1;
+            if (tid < 64) {
+                double m[NMOM], A[NMOM];
+#pragma unroll
+                for (int q = 0; q < NMOM; ++q) {
+                    m[q] = Ms[q];
+                    A[q] = Ms[13 + q];
+                }
+                const int ns_after = nsamp + ((int)step >= I.avg_start ? 1 : 0);
+                const CellF fw = pair_derive(I, m, nlog, A,
+                                             I.jmom_mode == 1 && (ns_after > 0 || I.avg_init), tid);
+                if (tid == 0) f = fw;
+            }
+            wg_sync<NT>();
+            int n2w = spawn_count(I, 2, c, mstep, f, L.pre[39], nullptr);
+            if (nlog + n2w > I.max_ppc || nphys + n2w > CAP) {
+                if (nlog + n2w <= I.max_ppc) return defer(2);
+                // the fused pass clamps the batch to the room left here
+                n2w = I.max_ppc - nlog < CAP - nphys ? I.max_ppc - nlog : CAP - nphys;
+                n2w = n2w < 0 ? 0 : n2w;
+            }
+            if (XB && I.open_mask) {
+                int ninw = 0;
+#pragma unroll
+                for (int fc = 0; fc < 4; ++fc) ninw += inject_count<DIM>(I, c, ix, iy, fc, mstep);
+                const int need_log = nlog + n2w + ninw, need_phys = nphys + n2w + ninw;
+                if ((need_log > I.max_ppc || need_phys > CAP) && need_log <= I.max_ppc)
+                    return defer(2);
+            }
+        }
         commit();
         // stay layout: every live particle at its logical slot of its own cell
 #pragma unroll
