@@ -449,6 +449,46 @@ def test_step_calls_split_anywhere_give_the_same_state(name):
         c.close()
 
 
+@pytest.mark.gpu
+def test_split_calls_agree_where_cells_straddle_the_one_wave_capacity():
+    """a near-continuum cavity (Kn = 1e-3: nu_ES dt > 1, so every added
+    batch has its full S0 / r_p particles) of 150 particles per cell in the
+    4-slot one-wave shape (256 slots): the particles of a relaxed cell plus
+    the next move's step-2 batch land on both sides of the capacity, so
+    cells are handed on early (the estimate), late in the fused pass (at
+    the step-2 batch) and at the end of a pass that only relaxes.  Every
+    split of 8 steps into calls gives the same state bit for bit, and both
+    kinds of cell occur (about 6 % go to a workgroup shape).  Without the
+    test at the end of the relax-only pass, the run of one step per call
+    parts from the others."""
+    usp = _gpu()
+    pb = P.cavity_2d(Kn=1e-3, n=16, ppc=150, seed=31)
+    c = usp.Context(0)
+    try:
+        xs = [c.add(pb) for _ in range(3)]
+        for x in xs:
+            x.set_shape(W4)
+        xs[0].set_diag(True)
+        c.step([xs[0]], 8)
+        for _ in range(8):
+            c.step([xs[1]], 1)
+        for k in (3, 1, 4):
+            c.step([xs[2]], k)
+        c.sync()
+        sa = xs[0].get_state()
+        for x in xs[1:]:
+            sx = x.get_state()
+            assert np.array_equal(sa.counts, sx.counts)
+            assert np.array_equal(sa.parts, sx.parts)
+            assert np.array_equal(sa.cells, sx.cells)
+        slots = xs[0].diag()[:, 47]  # slots of the shape that took each cell
+        big = float(np.mean(slots > 256))
+        print("cells in a workgroup shape: %.3f" % big)
+        assert 0.01 < big < 0.99
+    finally:
+        c.close()
+
+
 W4, W6 = 5, 6  # the one-wave shapes (64 threads x 4 and x 6 slots)
 XB_CASES = {"slit_fp32", "slit_fp64_vacuum", "sod_open_fp32", "open_channel_fp64",
             "effusion_fp32", "empty_start_fp32", "slit_fp32_far"}
