@@ -399,10 +399,11 @@ def open_channel_1d(Kn=0.1, ncell=50, ppc=100, n_hi=1.0, T_lo=273.0, T_hi=273.0,
 def slit_2d(Kn=0.01, a_cells=20, ppc=100, p_ratio=2.0, T1=273.0, n1=1.0e20, omega=0.5,
             precision=32, seed=0, pne_mode=PNE_GLL_AVG, jmom_mode=JMOM_AVG,
             spawn_projection=0, avg_init=1, n_avg=300, weight_mode=WEIGHT_LITERAL, cfl=0.3,
-            name="slit") -> Problem:
+            extent=10, name="slit") -> Problem:
     """Flow through a slit of width a between two chambers (Section 4.5),
-    half domain by the symmetry plane y = 0: x in [-10a, 10a], y in [0, 10a],
-    cell size a / a_cells (400 x 200 cells at a_cells = 20).  A thin diffuse
+    half domain by the symmetry plane y = 0: x in [-E a, E a], y in [0, E a]
+    with E = extent (10: the paper's domain height 20a), cell size
+    a / a_cells (400 x 200 cells at a_cells = 20).  A thin diffuse
     plate at T1 on x = 0 for y >= a/2; specular symmetry plane at y = 0; open
     faces to the upstream reservoir (n1, T1) on the left and on the top of
     the left chamber, to the downstream reservoir (n1 / p_ratio, T1) on the
@@ -424,21 +425,21 @@ def slit_2d(Kn=0.01, a_cells=20, ppc=100, p_ratio=2.0, T1=273.0, n1=1.0e20, omeg
     lam1 = gas.mean_free_path(gas.m * n1, p1, T1)
     a = lam1 / Kn
     d = a / a_cells
-    nx, ny = 20 * a_cells, 10 * a_cells
-    xs = -10.0 * a + (np.arange(nx) + 0.5) * d
+    nx, ny = 2 * extent * a_cells, extent * a_cells
+    xs = -extent * a + (np.arange(nx) + 0.5) * d
     n = np.tile(np.where(xs < 0.0, n1, n2), ny)
     nc = nx * ny
     faces = [Face(BC_OPEN, T1, n=n1), Face(BC_OPEN, T1, n=n2), Face(BC_SPECULAR),
              Face(BC_OPEN, T1, n=n1, split=0.0, n_b=n2, T_b=T1)]
-    return _sized(Problem(name=name, gas=gas, dim=2, nx=nx, ny=ny, x0=-10.0 * a, x1=10.0 * a,
-                   y0=0.0, y1=10.0 * a, dx=d, dy=d, inv_dx=1.0 / d, inv_dy=1.0 / d,
+    return _sized(Problem(name=name, gas=gas, dim=2, nx=nx, ny=ny, x0=-extent * a,
+                   x1=extent * a, y0=0.0, y1=extent * a, dx=d, dy=d, inv_dx=1.0 / d, inv_dy=1.0 / d,
                    vcell=d * d, faces=faces, accel=(0.0, 0.0, 0.0),
                    dt=cfl * d / gas.mean_speed(T1), Np=0.5 * (n1 + n2) * d * d / ppc,
                    init_n=n, init_u=np.zeros((nc, 3)), init_T=np.full(nc, T1),
                    precision=precision, seed=seed, pne_mode=pne_mode, jmom_mode=jmom_mode,
                    spawn_projection=spawn_projection, avg_init=avg_init, n_avg=n_avg,
                    weight_mode=weight_mode, plate=1, plate_x=0.0,
-                   plate_ylo=0.5 * a, plate_yhi=10.0 * a, plate_T=T1,
+                   plate_ylo=0.5 * a, plate_yhi=extent * a, plate_T=T1,
                    meta=dict(a=a, lam1=lam1, n1=n1, n2=n2, p1=p1, T1=T1, Kn=Kn)))
 
 

@@ -2,15 +2,20 @@
 reduced mass flow rate of the slit into vacuum at delta = 20 (Section 4.5,
 Eq. 40-41; tests/golden/slit_mass_flow.txt).
 
-The 400 x 200 half domain of the slit workload (chambers 10a wide and 10a
-high, cell a/20, dt = 0.3 dx / mean speed), upstream reservoir at n1 = 1e20
-m^-3 and 273 K, vacuum downstream.  delta = a p1 / (mu1 v1) relates to the
-Knudsen number of the builder (lambda of Eq. 36 over a) by Kn = 16 / (10
-sqrt(pi) delta).  The mass flow through the slit is, in the steady state,
-the flux through any vertical line next to the plate: the columns of cells
-on either side of x = 0 (the plate's faces carry no net flux), sum over y of
-rho u_x dy, doubled for the lower half; averaged over the last two thirds
-of 8000 steps.
+The half domain by the symmetry plane, with chambers reaching 20a from the
+slit (x in [-20a, 20a], y in [0, 20a]: the paper gives the computational
+domain a height of 20a and computes the upper half; read as the height of
+that half), cell a/20 (800 x 400), dt = 0.3 dx / mean speed = 0.33 tau_c,
+upstream reservoir at n1 = 1e20 m^-3 and 273 K, vacuum downstream.  delta =
+a p1 / (mu1 v1) relates to the Knudsen number of the builder (lambda of
+Eq. 36 over a) by Kn = 16 / (10 sqrt(pi) delta).  The mass flow through the
+slit is, in the steady state, the flux through any vertical line next to the
+plate: the columns of cells on either side of x = 0 (the plate's faces
+carry no net flux), sum over y of rho u_x dy, doubled for the lower half;
+averaged over the last two thirds of 12000 steps (4000 tau_c).  Measured
+with three seeds: 1.536, 1.525, 1.535; with chambers of 10a (the 400 x 200
+workload) W is 1.3 % lower (1.513 - 1.519), of 15a 1.0 % lower: a
+reservoir face close to the slit lowers the flow.
 """
 import math
 import os
@@ -46,7 +51,8 @@ def test_slit_reduced_mass_flow_rate_at_delta_20():
     from paper_1808_03801_amd import usp
     delta = 20.0
     W_ref = _golden()[delta]
-    pb = P.slit_2d(Kn=16.0 / (10.0 * math.sqrt(math.pi)) / delta, p_ratio=math.inf, seed=7)
+    pb = P.slit_2d(Kn=16.0 / (10.0 * math.sqrt(math.pi)) / delta, p_ratio=math.inf, extent=20,
+                   seed=7)
     a, p1 = pb.meta["a"], pb.meta["p1"]
     v1 = math.sqrt(2 * pb.gas.kB * 273.0 / pb.gas.m)
     m_fm = a * p1 / (math.sqrt(math.pi) * v1)
@@ -55,13 +61,13 @@ def test_slit_reduced_mass_flow_rate_at_delta_20():
     try:
         ctx.set_graph(True)
         g = ctx.add(pb)
-        steps, acc = 8000, []
-        for k in range(steps // 10):
-            ctx.step([g], 10)
-            if (k + 1) % 50 == 0:
+        steps, every, acc = 12000, 10, []
+        for k in range(steps // every):
+            ctx.step([g], every)
+            if (k + 1) % 200 == 0:
                 ctx.sync()
-                print("step", (k + 1) * 10, flush=True)
-            if (k + 1) * 10 > steps // 3:
+                print("step", (k + 1) * every, flush=True)
+            if (k + 1) * every > steps // 3:
                 f = g.fields(0).reshape(pb.ny, pb.nx, -1)
                 flux = f[:, :, 1] * f[:, :, 2]
                 acc.append(flux[:, half - 1:half + 1].sum(axis=0) * pb.dy)
