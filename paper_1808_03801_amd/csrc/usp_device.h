@@ -101,16 +101,21 @@ __device__ __forceinline__ void derive(const InstDev& I, const double* m, int n,
     f.rho = I.F * f.S0;
     f.p = I.F * third;
     f.T = f.theta / I.R;
-    f.mu = I.mu_ref * pow(f.T / I.T_ref, I.omega);
+    // Eq. 35; the square root for hard spheres (omega = 1/2), a tenth of
+    // the instructions of the general power
+    const double tr = f.T / I.T_ref;
+    f.mu = I.mu_ref * (I.omega == 0.5 ? sqrt(tr) : pow(tr, I.omega));
     f.nu = f.p / f.mu;
     f.x = I.Pr * f.nu * I.dt;
-    f.s[0] = (m[4] - third) / third;
-    f.s[1] = (m[5] - third) / third;
-    f.s[2] = (m[6] - third) / third;
-    f.s[3] = m[7] / third;
-    f.s[4] = m[8] / third;
-    f.s[5] = m[9] / third;
-    for (int k = 0; k < 3; ++k) f.h[k] = 0.5 * m[10 + k] / third;
+    // sigma / p and q / p: one division, then products
+    const double inv = 1.0 / third;
+    f.s[0] = (m[4] - third) * inv;
+    f.s[1] = (m[5] - third) * inv;
+    f.s[2] = (m[6] - third) * inv;
+    f.s[3] = m[7] * inv;
+    f.s[4] = m[8] * inv;
+    f.s[5] = m[9] * inv;
+    for (int k = 0; k < 3; ++k) f.h[k] = 0.5 * m[10 + k] * inv;
 }
 
 // centred moments from raw sums (S0, S1[3], S2[6], S3[3])
