@@ -126,8 +126,12 @@ template <int NT, int K>
 __device__ __forceinline__ void bsum(double (&v)[K], double* red, int tid)
 {
     constexpr int NW = NT / 64;
+    if constexpr (K >= 4) {
+        wave_sums<K>(v);
+    } else {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+        for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    }
     if constexpr (NW == 1) return;  // one wave: every lane holds the total
     const int lane = tid & 63, wave = tid >> 6;
     wg_sync<NT>();

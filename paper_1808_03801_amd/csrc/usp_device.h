@@ -198,6 +198,65 @@ __device__ __forceinline__ double wave_sum(double v)
     return readlane_d(v, 63);
 }
 
+// K sums over the 64 lanes of a wavefront at once (all lanes active), every
+// total returned in every lane.  The two cross-row levels are a
+// reduce-scatter on the lane swaps of gfx950: swapping lanes 32-63 of one
+// value with lanes 0-31 of another and adding leaves, in one register, the
+// half-sums of both (one per half of the wave); the 16-lane swap of the odd
+// rows of one such register with the even rows of another leaves four
+// values, one per row, as 16 partial sums each.  Row shifts by 1, 2, 4, 8
+// then finish every row in its lane 15.  About a third of the instructions
+// of K single sums; the order of additions is fixed, so the totals are
+// deterministic and identical in all lanes.
+__device__ __forceinline__ void swap32_d(double& a, double& b)
+{
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a),
+                                                     (unsigned)__double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a),
+                                                     (unsigned)__double2hiint(b), false, false);
+    a = __hiloint2double((int)hi[0], (int)lo[0]);
+    b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+__device__ __forceinline__ void swap16_d(double& a, double& b)
+{
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a),
+                                                     (unsigned)__double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a),
+                                                     (unsigned)__double2hiint(b), false, false);
+    a = __hiloint2double((int)hi[0], (int)lo[0]);
+    b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+template <int K>
+__device__ __forceinline__ void wave_sums(double (&v)[K])
+{
+    constexpr int K4 = (K + 3) / 4 * 4, H = K4 / 2, Q = K4 / 4;
+    double w[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        // lanes 0-31: value i, lanes 32-63: value i + H, each over lane pairs
+        // (l, l + 32)
+        double a = i < K ? v[i] : 0.0, b = i + H < K ? v[i + H] : 0.0;
+        swap32_d(a, b);
+        w[i] = a + b;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        // row r: value i + r Q over lane quadruples (l, l + 16, l + 32, l + 48)
+        double a = w[i], b = w[i + Q];
+        swap16_d(a, b);
+        double x = a + b;
+        x += dpp_d<0x111, 0xF>(x);  // row_shr:1
+        x += dpp_d<0x112, 0xF>(x);  // row_shr:2
+        x += dpp_d<0x114, 0xF>(x);  // row_shr:4
+        x += dpp_d<0x118, 0xF>(x);  // row_shr:8
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (i + r * Q < K) v[i + r * Q] = readlane_d(x, 16 * r + 15);
+    }
+}
+
 __device__ __forceinline__ double wave_min(double v)
 {
 #pragma unroll
