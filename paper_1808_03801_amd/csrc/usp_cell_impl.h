@@ -253,8 +253,8 @@ __device__ __forceinline__ int fate(const Parts<real, DIM, PPT>& P, int k)
 // pass, centred from them; E = sum w |c|^2 / 2.  Every thread gets the results.
 // ---------------------------------------------------------------------------
 template <int NT, typename real, int DIM, int PPT>
-__device__ void moments_r(const Parts<real, DIM, PPT>& P, const Lds& L, int tid, int nuse,
-                          double* cen, double* raw, double* E)
+__device__ __forceinline__ void moments_r(const Parts<real, DIM, PPT>& P, const Lds& L, int tid,
+                                          int nuse, double* cen, double* raw, double* E)
 {
     double a[14];
 #pragma unroll
@@ -320,9 +320,10 @@ __device__ __forceinline__ int spawn_count(const InstDev& I, int batch, int cell
 }
 
 template <int NT, typename real, int DIM, int PPT>
-__device__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L, int batch,
-                       int cell, int ix, int iy, uint32_t step, const CellF& f, double pne, int a,
-                       int ls, int tid, uint32_t* errbits, double* marg, bool can_defer)
+__device__ __forceinline__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& P, const Lds& L,
+                                       int batch, int cell, int ix, int iy, uint32_t step,
+                                       const CellF& f, double pne, int a, int ls, int tid,
+                                       uint32_t* errbits, double* marg, bool can_defer)
 {
     if (!f.valid || !(pne > 0.0) || !(f.x > 0.0)) return 0;
     const double m1 = f.x < 1.0 ? f.x : 1.0;
