@@ -61,6 +61,7 @@ enum { USP_JMOM_INST = 0, USP_JMOM_AVG = 1 };
 enum { USP_SCHEME_USP = 0, USP_SCHEME_SP = 1 };
 enum { USP_ES_SAMPLED = 0, USP_ES_MEAN = 1 };
 enum { USP_GLL_U_SOUND = 0, USP_GLL_U_LITERAL = 1 };
+enum { USP_SELECT_BERNOULLI = 0, USP_SELECT_COUNT = 1 };
 
 /* Gas (Section 4): Eq. 35 viscosity mu = mu_ref (T / T_ref)^omega; Pr of
  * Eq. 6 (nu_ES = Pr nu); molecular mass m and Boltzmann constant kB. */
@@ -139,7 +140,12 @@ typedef struct {
  * gll_u: the velocity term of Eq. 18, lambda |grad |u|| / Q: USP_GLL_U_SOUND
  * (Q = max(|u|, sqrt(5 theta / 3)), the convention of the GLL criterion's
  * authors; finite at stagnation) or USP_GLL_U_LITERAL (Q = |u| as printed;
- * a cell at rest with a velocity gradient gets P_ne = 0). */
+ * a cell at rest with a velocity gradient gets P_ne = 0).
+ * select_mode: step 5 of USP-ESBGK: USP_SELECT_BERNOULLI (each particle
+ * selected with probability 1 - exp(-nu_ES dt), the rate of Eq. 9) or
+ * USP_SELECT_COUNT (Eq. 9 as printed: N_s = nearest(N_c (1 - exp(-nu_ES
+ * dt))) particles of the cell, the ones with the smallest rank keys, are
+ * the selected ones; Eq. 28 then keeps int(sum of their weights)). */
 typedef struct {
     double dt, Np, r_p, Kn_c, pne_fixed;
     int pne_mode, n_avg, avg_start, precision, weight_mode, conserve_mode, max_ppc;
@@ -149,6 +155,7 @@ typedef struct {
     int scheme;
     int es_mode;
     int gll_u;
+    int select_mode;
 } usp_numerics;
 
 /* Device binding.  alloc/free: device allocator (NULL = hipMalloc/hipFree);

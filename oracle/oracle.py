@@ -50,6 +50,7 @@ class Config(C.Structure):
         ("plate_yhi", C.c_double), ("plate_T", C.c_double), ("scheme", C.c_int),
         ("es_mode", C.c_int),
         ("gll_u", C.c_int),
+        ("select_mode", C.c_int),
     ]
 
 
@@ -122,6 +123,7 @@ def make_config(pb) -> Config:
     g.scheme = pb.scheme
     g.es_mode = pb.es_mode
     g.gll_u = pb.gll_u
+    g.select_mode = pb.select_mode
     for k in range(3):
         g.accel[k] = pb.accel[k]
     g.dt, g.Np, g.r_p, g.Kn_c, g.pne_fixed = pb.dt, pb.Np, pb.r_p, pb.Kn_c, pb.pne_fixed

@@ -38,7 +38,8 @@
  * uses P^{n-1}; the count of added particles (Eq. 25) is stochastically
  * rounded; the added-particle weight is r_p (dt J/2) / (f_e min(1, nu_ES dt)),
  * which equals Eq. 26 when nu_ES dt >= 1; selection is a per-particle
- * Bernoulli trial at the rate of Eq. 9; the particles kept by Eq. 28 are the
+ * Bernoulli trial at the rate of Eq. 9 (select_mode 1: Eq. 9's count as
+ * printed, the N_s smallest rank keys); the particles kept by Eq. 28 are the
  * selected ones with the smallest random rank keys; the velocity term of
  * the GLL Knudsen number (Eq. 18) is taken over max(|u|, sqrt(5 theta / 3))
  * unless gll_u asks for |u| as printed.
@@ -973,26 +974,46 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
 
         /* step 5: Bernoulli selection with probability 1 - exp(-nu_ES dt);
          * SP-ESBGK: every particle is a candidate and Eq. 9 fixes how many
-         * of them are reassigned (S = N_c (1 - exp(-nu_ES dt))) */
+         * of them are reassigned (S = N_c (1 - exp(-nu_ES dt))); with
+         * select_mode 1 (Eq. 9 as printed for USP-ESBGK) the N_s =
+         * nearest(N_c (1 - exp(-nu_ES dt))) particles with the smallest rank
+         * keys are the selected ones */
         double psel = -expm1(-f.x);
         dg[D_PSEL] = psel;
         selinfo* si = (selinfo*)calloc((size_t)nl + 1, sizeof(selinfo));
-        double S = 0.0;
-        int ns = 0;
+        const int count_mode = g->scheme != 1 && g->select_mode == 1;
         for (int i = 0; i < nl; ++i) {
             uint32_t r[4];
             draw(g, (uint32_t)o->step, PUR_SELECT, 0, (uint32_t)d, (uint32_t)i, r);
             double u = uspo_uniform(r[0], g->precision);
-            si[i].sel = g->scheme == 1 ? 1 : u < psel;
+            si[i].sel = (g->scheme == 1 || count_mode) ? 1 : u < psel;
             double mg = fabs(u - psel);
-            if (g->scheme != 1 && mg < dg[D_MARG_SEL]) dg[D_MARG_SEL] = mg;
+            if (g->scheme != 1 && !count_mode && mg < dg[D_MARG_SEL]) dg[D_MARG_SEL] = mg;
             si[i].rank = (r[1] & 0xFFFFF800u) | (uint32_t)i;
             si[i].ut = uspo_uniform(r[2], g->precision);
+        }
+        if (count_mode && nl > 0) {
+            /* Eq. 9: nearest integer of N_c (1 - exp(-nu_ES dt)), then the
+             * N_s smallest rank keys of the cell */
+            const double v = (double)nl * psel;
+            int nsel = (int)floor(v + 0.5);
+            if (nsel > nl) nsel = nl;
+            if (nsel < 0) nsel = 0;
+            dg[D_MARG_SEL] = fabs(v - (floor(v) + 0.5));
+            uint32_t* all = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)nl);
+            for (int i = 0; i < nl; ++i) all[i] = si[i].rank;
+            qsort(all, (size_t)nl, sizeof(uint32_t), cmp_rank);
+            const uint32_t ths = nsel > 0 ? all[nsel - 1] : 0;
+            free(all);
+            for (int i = 0; i < nl; ++i) si[i].sel = nsel > 0 && si[i].rank <= ths;
+        }
+        double S = 0.0;
+        int ns = 0;
+        for (int i = 0; i < nl; ++i)
             if (si[i].sel) {
                 S += L->p[i].w;
                 ++ns;
             }
-        }
         if (g->scheme == 1) S = (double)ns * psel;
         /* Eq. 28 (Eq. 9 for SP-ESBGK): int() = nearest integer, clamped to
          * [0, N_s] */
@@ -1274,6 +1295,7 @@ static int check_config(const uspo_config* g)
     if (g->scheme != 0 && g->scheme != 1) return -1;
     if (g->es_mode != 0 && g->es_mode != 1) return -1;
     if (g->gll_u != 0 && g->gll_u != 1) return -1;
+    if (g->select_mode != 0 && g->select_mode != 1) return -1;
     if (g->es_mode == 1 && !(g->Pr > 0.0 && g->Pr != 1.0)) return -1;
     /* SP-ESBGK has no added particles: P_ne fixed at 0 */
     if (g->scheme == 1 && !(g->pne_mode == 0 && g->pne_fixed == 0.0)) return -1;

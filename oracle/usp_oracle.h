@@ -70,6 +70,10 @@ typedef struct {
     /* velocity term of Eq. 18: 0 = lambda |grad |u|| / max(|u|, sqrt(5 theta
      * / 3)); 1 = lambda |grad |u|| / |u| as printed */
     int gll_u;
+    /* step 5 of USP-ESBGK: 0 = each particle selected with probability
+     * 1 - exp(-nu_ES dt); 1 = Eq. 9 as printed: N_s = nearest(N_c (1 -
+     * exp(-nu_ES dt))) particles, the ones with the smallest rank keys */
+    int select_mode;
 } uspo_config;
 
 /* per-cell state record: centred moments, raw sums, averaged raw sums of f^n,

@@ -610,8 +610,8 @@ __device__ __forceinline__ int resample_one(const InstDev& I, int cell, int slot
 // collected (into the gather map, free during the relaxation) and ranked
 // exactly by wave 0.  Keys are distinct (they end in the slot).
 template <int NT, typename real, int DIM, int PPT>
-__device__ uint32_t kth_key_r(const Parts<real, DIM, PPT>& P, const Lds& L, int kth, int nuse,
-                              int tid)
+__device__ __forceinline__ uint32_t kth_key_r(const Parts<real, DIM, PPT>& P, const Lds& L, int kth,
+                                              int nuse, int tid)
 {
     constexpr int NB = lds_dims(NT).kth;
     constexpr int SH = NB == 64 ? 26 : 21;  // bucket = the key's top log2(NB) bits
@@ -1045,6 +1045,8 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             mark(2);
             // step 5
             const bool sp = I.scheme == 1;
+            // Eq. 9's count as printed: the N_s smallest rank keys are selected
+            const bool cnt = !sp && I.select_mode == 1;
             const double psel = -expm1(-f.x);
             double ss[2] = {0.0, 0.0};
             double msel = __builtin_inf();
@@ -1058,16 +1060,37 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
                     draw(I, step, PUR_SELECT, 0u, (uint32_t)c, (uint32_t)j, r);
                     const double u = uni_d(r[0], I.prec);
                     // SP-ESBGK: every particle is a candidate (Eq. 9 counts them)
-                    const bool sel = sp || u < psel;
-                    if (!sp) msel = fmin(msel, fabs(u - psel));
+                    const bool sel = sp || cnt || u < psel;
+                    if (!sp && !cnt) msel = fmin(msel, fabs(u - psel));
                     P.key[k] = (r[1] & 0xFFFFF800u) | (uint32_t)j;
                     rtime[k] = r[2];
                     if (sel) {
                         P.st[k] = (P.st[k] & ~0xFFu) | FT_SEL;
-                        ss[0] += (double)P.w[k];
-                        ss[1] += 1.0;
+                        if (!cnt) {
+                            ss[0] += (double)P.w[k];
+                            ss[1] += 1.0;
+                        }
                     }
                 }
+            }
+            if (cnt) {
+                // N_s = nearest(N_c (1 - exp(-nu_ES dt))); the others go back
+                const double v = (double)nl * psel;
+                int nsel = (int)floor(v + 0.5);
+                nsel = nsel < 0 ? 0 : (nsel > nl ? nl : nsel);
+                msel = fabs(v - (floor(v) + 0.5));
+                uint32_t ths = 0;
+                if (nsel > 0 && nsel < nl) ths = kth_key_r<NT>(P, L, nsel, nlu, tid);
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+                    if (k * NT < nlu && fate(P, k) == FT_SEL) {
+                        if (nsel == 0 || (nsel < nl && P.key[k] > ths)) {
+                            P.st[k] = (P.st[k] & ~0xFFu) | FT_KEEP;
+                        } else {
+                            ss[0] += (double)P.w[k];
+                            ss[1] += 1.0;
+                        }
+                    }
             }
             bsum<NT>(ss, L.red, tid);
             if (dg) msel = bmin<NT>(msel, L.red, tid);

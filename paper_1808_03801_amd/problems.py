@@ -55,6 +55,8 @@ ES_SAMPLED, ES_MEAN = 0, 1
 # velocity term of the GLL Knudsen number (Eq. 18): lambda |grad |u|| over
 # max(|u|, sound speed) (the criterion's authors' convention) or over |u|
 GLL_U_SOUND, GLL_U_LITERAL = 0, 1
+# step 5 of USP-ESBGK: a Bernoulli trial per particle, or Eq. 9's count
+SELECT_BERNOULLI, SELECT_COUNT = 0, 1
 
 FACE_XLO, FACE_XHI, FACE_YLO, FACE_YHI = 0, 1, 2, 3
 
@@ -158,6 +160,7 @@ class Problem:
     scheme: int = SCHEME_USP
     es_mode: int = ES_SAMPLED
     gll_u: int = GLL_U_SOUND
+    select_mode: int = SELECT_BERNOULLI
     meta: dict = field(default_factory=dict)
 
     @property

@@ -94,6 +94,13 @@ def _cases():
         "c1_gll_literal_fp64": lambda: P.couette_1d(ncell=40, ppc=100, seed=32,
                                                     pne_mode=P.PNE_GLL_INST).replace(
             gll_u=P.GLL_U_LITERAL),
+        # step 5 with Eq. 9's count as printed (the N_s smallest rank keys)
+        "c1_count_fp64": lambda: P.couette_1d(ncell=40, ppc=100, seed=33).replace(
+            select_mode=P.SELECT_COUNT),
+        "thermal_couette_count_fp32": lambda: P.thermal_couette_1d(
+            ncell=120, ppc=200, Kn=1e-2, seed=34).replace(select_mode=P.SELECT_COUNT),
+        "cavity_count_fp32": lambda: P.cavity_2d(Kn=0.01, n=16, ppc=80, seed=35).replace(
+            select_mode=P.SELECT_COUNT),
         # the SP-ESBGK baseline (Table 1)
         "c1_sp_fp64": lambda: P.sp_esbgk(P.couette_1d(ncell=40, ppc=100, seed=25)),
         "cavity_sp_fp32": lambda: P.sp_esbgk(P.cavity_2d(Kn=0.01, n=16, ppc=80, seed=26)),
@@ -282,7 +289,7 @@ def test_mode_switches_outside_their_values_are_refused(ctx):
     pb = _cases()["thermal_couette_fp32"]()
     for field, bad in (("pne_mode", 3), ("weight_mode", 2), ("conserve_mode", -1),
                        ("jmom_mode", 2), ("spawn_projection", 2), ("avg_init", 5),
-                       ("scheme", 2), ("es_mode", 2), ("gll_u", 2)):
+                       ("scheme", 2), ("es_mode", 2), ("gll_u", 2), ("select_mode", 2)):
         with pytest.raises(usp.UspError) as e:
             ctx.add(pb.replace(**{field: bad}))
         assert e.value.status == -1, field
