@@ -62,6 +62,7 @@ enum { USP_SCHEME_USP = 0, USP_SCHEME_SP = 1 };
 enum { USP_ES_SAMPLED = 0, USP_ES_MEAN = 1 };
 enum { USP_GLL_U_SOUND = 0, USP_GLL_U_LITERAL = 1 };
 enum { USP_SELECT_BERNOULLI = 0, USP_SELECT_COUNT = 1 };
+enum { USP_ES_SAMPLER_CHOLESKY = 0, USP_ES_SAMPLER_LINEAR = 1 };
 
 /* Gas (Section 4): Eq. 35 viscosity mu = mu_ref (T / T_ref)^omega; Pr of
  * Eq. 6 (nu_ES = Pr nu); molecular mass m and Boltzmann constant kB. */
@@ -145,7 +146,16 @@ typedef struct {
  * selected with probability 1 - exp(-nu_ES dt), the rate of Eq. 9) or
  * USP_SELECT_COUNT (Eq. 9 as printed: N_s = nearest(N_c (1 - exp(-nu_ES
  * dt))) particles of the cell, the ones with the smallest rank keys, are
- * the selected ones; Eq. 28 then keeps int(sum of their weights)). */
+ * the selected ones; Eq. 28 then keeps int(sum of their weights)).
+ * es_sampler: step 6 sampler of f_G(t) (Eq. 32): USP_ES_SAMPLER_CHOLESKY
+ * (u + L z with L the Cholesky factor of its covariance theta I + (1 - 1/Pr)
+ * alpha sigma / rho, exact) or USP_ES_SAMPLER_LINEAR (the linear map of
+ * Eq. 10-11 with alpha sigma in place of sigma: u + sqrt(theta) S z, S = I -
+ * (1 - Pr) / (2 Pr) alpha sigma / p; covariance exact to first order in
+ * sigma / p, its trace above the target's by theta ((1 - Pr) / (2 Pr))^2
+ * alpha^2 tr((sigma / p)^2); theta S S^T is never indefinite, so no
+ * reassignment takes the isotropic fallback of the Cholesky sampler).
+ * Applies to USP_SCHEME_USP; the SP-ESBGK scheme always uses the map. */
 typedef struct {
     double dt, Np, r_p, Kn_c, pne_fixed;
     int pne_mode, n_avg, avg_start, precision, weight_mode, conserve_mode, max_ppc;
@@ -156,6 +166,7 @@ typedef struct {
     int es_mode;
     int gll_u;
     int select_mode;
+    int es_sampler;
 } usp_numerics;
 
 /* Device binding.  alloc/free: device allocator (NULL = hipMalloc/hipFree);

@@ -51,6 +51,7 @@ class Config(C.Structure):
         ("es_mode", C.c_int),
         ("gll_u", C.c_int),
         ("select_mode", C.c_int),
+        ("es_sampler", C.c_int),
     ]
 
 
@@ -124,6 +125,7 @@ def make_config(pb) -> Config:
     g.es_mode = pb.es_mode
     g.gll_u = pb.gll_u
     g.select_mode = pb.select_mode
+    g.es_sampler = pb.es_sampler
     for k in range(3):
         g.accel[k] = pb.accel[k]
     g.dt, g.Np, g.r_p, g.Kn_c, g.pne_fixed = pb.dt, pb.Np, pb.r_p, pb.Kn_c, pb.pne_fixed

@@ -774,13 +774,17 @@ static void totals(const part* p, int n, double* M, double P[3], double* E)
  * lambda(t) = theta (I + (1 - 1/Pr) alpha(t) s*), alpha = P + (1-P) e^{-nu t};
  * velocity u* + L z with L the Cholesky factor of lambda.  A pivot not above
  * 1e-12 theta falls back to the isotropic factor sqrt(theta) I. */
-/* SP-ESBGK (Table 1, steps 3-4): a Maxwellian thermal velocity at the
- * cell's temperature (Eq. 10) mapped by S = I - (1 - Pr) / (2 Pr) (p_ij /
- * (rho theta) - I) (Eq. 11), where p_ij / (rho theta) - I = sigma / p. */
-static void resample_sp(const uspo* o, const cellf* f, int cell, int slot, part* q)
+/* The linear map of Eq. 10-11: a Maxwellian thermal velocity at the cell's
+ * temperature mapped by S = I - (1 - Pr) / (2 Pr) a (p_ij / (rho theta) - I),
+ * where p_ij / (rho theta) - I = sigma / p; c = u + sqrt(theta) S z.  a = 1
+ * is SP-ESBGK's fixed target (Table 1, steps 3-4); a = alpha of Eq. 32 maps
+ * to USP-ESBGK's f_G(t) with es_sampler 1 (the covariance theta S S^T equals
+ * the target's to first order in sigma / p). */
+static void resample_linear(const uspo* o, const cellf* f, double a, int cell, int slot,
+                            part* q)
 {
     const uspo_config* g = &o->g;
-    double k = (1.0 - g->Pr) / (2.0 * g->Pr);
+    double k = (1.0 - g->Pr) / (2.0 * g->Pr) * a;
     double S00 = 1.0 - k * f->s[0], S11 = 1.0 - k * f->s[1], S22 = 1.0 - k * f->s[2];
     double S01 = -k * f->s[3], S02 = -k * f->s[4], S12 = -k * f->s[5];
     uint32_t r[4];
@@ -799,7 +803,7 @@ static int resample(const uspo* o, const cellf* f, double pne, int cell, int slo
 {
     const uspo_config* g = &o->g;
     if (g->scheme == 1) {
-        resample_sp(o, f, cell, slot, q);
+        resample_linear(o, f, 1.0, cell, slot, q);
         return 0;
     }
     double alpha;
@@ -813,6 +817,10 @@ static int resample(const uspo* o, const cellf* f, double pne, int cell, int slo
     } else {
         double t = uspo_time_sample(ut, f->x, g->Pr * f->nu, g->dt);
         alpha = pne + (1.0 - pne) * exp(-f->nu * t);
+    }
+    if (g->es_sampler == 1) {
+        resample_linear(o, f, alpha, cell, slot, q);
+        return 0;
     }
     double c = (1.0 - 1.0 / g->Pr) * alpha;
     double th = f->theta;
@@ -1296,6 +1304,7 @@ static int check_config(const uspo_config* g)
     if (g->es_mode != 0 && g->es_mode != 1) return -1;
     if (g->gll_u != 0 && g->gll_u != 1) return -1;
     if (g->select_mode != 0 && g->select_mode != 1) return -1;
+    if (g->es_sampler != 0 && g->es_sampler != 1) return -1;
     if (g->es_mode == 1 && !(g->Pr > 0.0 && g->Pr != 1.0)) return -1;
     /* SP-ESBGK has no added particles: P_ne fixed at 0 */
     if (g->scheme == 1 && !(g->pne_mode == 0 && g->pne_fixed == 0.0)) return -1;

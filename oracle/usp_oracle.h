@@ -74,6 +74,9 @@ typedef struct {
      * 1 - exp(-nu_ES dt); 1 = Eq. 9 as printed: N_s = nearest(N_c (1 -
      * exp(-nu_ES dt))) particles, the ones with the smallest rank keys */
     int select_mode;
+    /* step 6 sampler of f_G(t): 0 = FP64 Cholesky factor of its covariance;
+     * 1 = the linear map of Eq. 10-11 with alpha sigma in place of sigma */
+    int es_sampler;
 } uspo_config;
 
 /* per-cell state record: centred moments, raw sums, averaged raw sums of f^n,

@@ -548,6 +548,35 @@ __device__ __forceinline__ void es_draw(const InstDev& I, int cell, int slot, ui
     c2 = (real)(f.U[2] + L.L20 * z[0] + L.L21 * z[1] + L.L22 * z[2]);
 }
 
+// the linear map of Eq. 10-11: u + sqrt(theta) S z with S = I - (1 - Pr) /
+// (2 Pr) a sigma / p; a = 1 is SP-ESBGK's target, a = alpha of Eq. 32 maps to
+// f_G(t) (its covariance to first order in sigma / p).  z is the particle's
+// RESAMPLE draw, in single precision for FP32 state.
+template <typename real>
+__device__ __forceinline__ void lin_draw(const InstDev& I, int cell, int slot, uint32_t step,
+                                         const CellF& f, double a, real& c0, real& c1, real& c2)
+{
+    const double kk = (1.0 - I.Pr) / (2.0 * I.Pr) * a;
+    const double S00 = 1.0 - kk * f.s[0], S11 = 1.0 - kk * f.s[1], S22 = 1.0 - kk * f.s[2];
+    const double S01 = -kk * f.s[3], S02 = -kk * f.s[4], S12 = -kk * f.s[5];
+    uint32_t r[4];
+    draw(I, step, PUR_RESAMPLE, 0u, (uint32_t)cell, (uint32_t)slot, r);
+    double z[3];
+    if (sizeof(real) == 4) {
+        float zf[3];
+        normal3_f(r, zf);
+        z[0] = zf[0];
+        z[1] = zf[1];
+        z[2] = zf[2];
+    } else {
+        normal3_d(r, I.prec, z);
+    }
+    const double sq = sqrt(f.theta);
+    c0 = (real)(f.U[0] + sq * (S00 * z[0] + S01 * z[1] + S02 * z[2]));
+    c1 = (real)(f.U[1] + sq * (S01 * z[0] + S11 * z[1] + S12 * z[2]));
+    c2 = (real)(f.U[2] + sq * (S02 * z[0] + S12 * z[1] + S22 * z[2]));
+}
+
 // the expectation of alpha(t) (Eq. 32) over the Eq. 29-30 time distribution
 // (density nu_ES e^{nu_ES t} / (e^{nu_ES dt} - 1) on [0, dt])
 __device__ __forceinline__ double alpha_mean(const InstDev& I, const CellF& f, double pne)
@@ -562,30 +591,11 @@ __device__ __forceinline__ int resample_one(const InstDev& I, int cell, int slot
                                             const CellF& f, double pne, uint32_t rt, real& c0,
                                             real& c1, real& c2)
 {
-    uint32_t r[4];
     if (I.scheme == 1) {
-        // SP-ESBGK (Eq. 10-11): Maxwellian thermal velocity mapped by
-        // S = I - (1 - Pr) / (2 Pr) sigma / p around the cell's velocity
-        const double kk = (1.0 - I.Pr) / (2.0 * I.Pr);
-        const double S00 = 1.0 - kk * f.s[0], S11 = 1.0 - kk * f.s[1], S22 = 1.0 - kk * f.s[2];
-        const double S01 = -kk * f.s[3], S02 = -kk * f.s[4], S12 = -kk * f.s[5];
-        draw(I, step, PUR_RESAMPLE, 0u, (uint32_t)cell, (uint32_t)slot, r);
-        double z[3];
-        if (sizeof(real) == 4) {
-            float zf[3];
-            normal3_f(r, zf);
-            z[0] = zf[0];
-            z[1] = zf[1];
-            z[2] = zf[2];
-        } else {
-            normal3_d(r, I.prec, z);
-        }
-        const double sq = sqrt(f.theta);
-        c0 = (real)(f.U[0] + sq * (S00 * z[0] + S01 * z[1] + S02 * z[2]));
-        c1 = (real)(f.U[1] + sq * (S01 * z[0] + S11 * z[1] + S12 * z[2]));
-        c2 = (real)(f.U[2] + sq * (S02 * z[0] + S12 * z[1] + S22 * z[2]));
+        lin_draw<real>(I, cell, slot, step, f, 1.0, c0, c1, c2);
         return 0;
     }
+    uint32_t r[4];
     r[2] = rt;
     double alpha;
     if (sizeof(real) == 4) {
@@ -597,6 +607,10 @@ __device__ __forceinline__ int resample_one(const InstDev& I, int cell, int slot
         const double u = uni_d(r[2], I.prec);
         const double t = I.dt + log(u + (1.0 - u) * exp(-f.x)) / (I.Pr * f.nu);
         alpha = pne + (1.0 - pne) * exp(-f.nu * t);
+    }
+    if (I.es_sampler == 1) {
+        lin_draw<real>(I, cell, slot, step, f, alpha, c0, c1, c2);
+        return 0;
     }
     const EsFactor L = es_factor(I, f, alpha);
     es_draw<real>(I, cell, slot, step, f, L, c0, c1, c2);
@@ -1115,14 +1129,26 @@ __device__ __forceinline__ int process_cell_r(const InstDev& I, int c, int mode,
             double fbs[1] = {0.0};
             if (I.es_mode == 1 && !sp) {
                 // one Gaussian for the cell: alpha's expectation, one factor
-                const EsFactor Lc = es_factor(I, f, alpha_mean(I, f, Pn));
+                const double am = alpha_mean(I, f, Pn);
+                if (I.es_sampler == 1) {
 #pragma unroll
-                for (int k = 0; k < PPT; ++k)
-                    if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
-                        es_draw<real>(I, c, k * NT + tid, step, f, Lc, P.c0[k], P.c1[k], P.c2[k]);
-                        fbs[0] += (double)Lc.fb;
-                        P.w[k] = (real)1.0;
-                    }
+                    for (int k = 0; k < PPT; ++k)
+                        if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
+                            lin_draw<real>(I, c, k * NT + tid, step, f, am, P.c0[k], P.c1[k],
+                                           P.c2[k]);
+                            P.w[k] = (real)1.0;
+                        }
+                } else {
+                    const EsFactor Lc = es_factor(I, f, am);
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k)
+                        if (k * NT < nlu && fate(P, k) == FT_REASSIGN) {
+                            es_draw<real>(I, c, k * NT + tid, step, f, Lc, P.c0[k], P.c1[k],
+                                          P.c2[k]);
+                            fbs[0] += (double)Lc.fb;
+                            P.w[k] = (real)1.0;
+                        }
+                }
             } else {
 #pragma unroll
                 for (int k = 0; k < PPT; ++k)

@@ -91,6 +91,7 @@ struct InstDev {
     int es_mode;  // 0 alpha(t) per particle (Eq. 29-32), 1 its expectation per cell
     int gll_u;    // Eq. 18 velocity term over 0 max(|u|, sound speed), 1 |u|
     int select_mode;  // step 5: 0 Bernoulli trial per particle, 1 Eq. 9 count
+    int es_sampler;   // step 6: 0 Cholesky factor of f_G(t), 1 Eq. 11 linear map
     uint32_t key0, key1;
     // sort window: source offsets -Kx..Kx, -Ky..Ky; nb = (2Ky+1)(2Kx+1) bins
     int Kx, Ky, nbx, nb;

@@ -315,6 +315,8 @@ usp_status validate(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb, con
         return fail(ctx, USP_EINVAL, "unknown gll_u");
     if (nm->select_mode != USP_SELECT_BERNOULLI && nm->select_mode != USP_SELECT_COUNT)
         return fail(ctx, USP_EINVAL, "unknown select_mode");
+    if (nm->es_sampler != USP_ES_SAMPLER_CHOLESKY && nm->es_sampler != USP_ES_SAMPLER_LINEAR)
+        return fail(ctx, USP_EINVAL, "unknown es_sampler");
     if (nm->es_mode == USP_ES_MEAN && !(gas->Pr > 0.0 && gas->Pr != 1.0))
         return fail(ctx, USP_EINVAL, "es_mode MEAN needs 0 < Pr != 1");
     if (nm->scheme == USP_SCHEME_SP && !(nm->pne_mode == USP_PNE_FIXED && nm->pne_fixed == 0.0))
@@ -691,6 +693,7 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
     h.es_mode = nm->es_mode;
     h.gll_u = nm->gll_u;
     h.select_mode = nm->select_mode;
+    h.es_sampler = nm->es_sampler;
     h.key0 = (uint32_t)(nm->seed & 0xFFFFFFFFu);
     h.key1 = (uint32_t)(nm->seed >> 32);
     Window w = choose_window(gas, pb, nm, init_u, init_T);

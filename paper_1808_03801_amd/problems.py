@@ -57,6 +57,8 @@ ES_SAMPLED, ES_MEAN = 0, 1
 GLL_U_SOUND, GLL_U_LITERAL = 0, 1
 # step 5 of USP-ESBGK: a Bernoulli trial per particle, or Eq. 9's count
 SELECT_BERNOULLI, SELECT_COUNT = 0, 1
+# step 6 sampler of f_G(t): its Cholesky factor, or Eq. 11's linear map
+ES_CHOLESKY, ES_LINEAR = 0, 1
 
 FACE_XLO, FACE_XHI, FACE_YLO, FACE_YHI = 0, 1, 2, 3
 
@@ -161,6 +163,7 @@ class Problem:
     es_mode: int = ES_SAMPLED
     gll_u: int = GLL_U_SOUND
     select_mode: int = SELECT_BERNOULLI
+    es_sampler: int = ES_CHOLESKY
     meta: dict = field(default_factory=dict)
 
     @property

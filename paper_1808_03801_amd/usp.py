@@ -55,7 +55,8 @@ class Numerics(C.Structure):
                                        "weight_mode", "conserve_mode", "max_ppc", "jmom_mode",
                                        "spawn_projection", "window")] + \
                [("seed", C.c_uint64), ("avg_init", C.c_int), ("scheme", C.c_int),
-                ("es_mode", C.c_int), ("gll_u", C.c_int), ("select_mode", C.c_int)]
+                ("es_mode", C.c_int), ("gll_u", C.c_int), ("select_mode", C.c_int),
+                ("es_sampler", C.c_int)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -197,6 +198,7 @@ def to_c(pb):
     nm.es_mode = int(pb.es_mode)
     nm.gll_u = int(pb.gll_u)
     nm.select_mode = int(pb.select_mode)
+    nm.es_sampler = int(pb.es_sampler)
     return gas, p, nm
 
 

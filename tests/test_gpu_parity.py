@@ -101,6 +101,15 @@ def _cases():
             ncell=120, ppc=200, Kn=1e-2, seed=34).replace(select_mode=P.SELECT_COUNT),
         "cavity_count_fp32": lambda: P.cavity_2d(Kn=0.01, n=16, ppc=80, seed=35).replace(
             select_mode=P.SELECT_COUNT),
+        # step 6 through the linear map of Eq. 11 with alpha sigma (per-particle
+        # alpha, and alpha's expectation per cell)
+        "c1_eslinear_fp64": lambda: P.couette_1d(ncell=40, ppc=100, seed=36).replace(
+            es_sampler=P.ES_LINEAR),
+        "thermal_couette_eslinear_fp32": lambda: P.thermal_couette_1d(
+            ncell=120, ppc=200, Kn=1e-2, seed=37).replace(es_sampler=P.ES_LINEAR),
+        "cavity_eslinear_esmean_fp32": lambda: P.cavity_2d(Kn=0.01, n=16, ppc=80,
+                                                           seed=38).replace(
+            es_sampler=P.ES_LINEAR, es_mode=P.ES_MEAN),
         # the SP-ESBGK baseline (Table 1)
         "c1_sp_fp64": lambda: P.sp_esbgk(P.couette_1d(ncell=40, ppc=100, seed=25)),
         "cavity_sp_fp32": lambda: P.sp_esbgk(P.cavity_2d(Kn=0.01, n=16, ppc=80, seed=26)),
@@ -289,7 +298,8 @@ def test_mode_switches_outside_their_values_are_refused(ctx):
     pb = _cases()["thermal_couette_fp32"]()
     for field, bad in (("pne_mode", 3), ("weight_mode", 2), ("conserve_mode", -1),
                        ("jmom_mode", 2), ("spawn_projection", 2), ("avg_init", 5),
-                       ("scheme", 2), ("es_mode", 2), ("gll_u", 2), ("select_mode", 2)):
+                       ("scheme", 2), ("es_mode", 2), ("gll_u", 2), ("select_mode", 2),
+                       ("es_sampler", 2)):
         with pytest.raises(usp.UspError) as e:
             ctx.add(pb.replace(**{field: bad}))
         assert e.value.status == -1, field
