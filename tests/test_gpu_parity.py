@@ -544,10 +544,14 @@ def test_wave_shapes_agree_with_each_other(name):
 
 
 def _family_cases():
+    """every launch shape as the first one (a workgroup shape above an
+    instance's last is taken as its last), over both precisions, both
+    dimensions and both boundary variants"""
     out = []
     for name in ("cavity_fp32", "sod_fp32", "slit_fp32", "c1_couette_fp64", "sod_fp32_tiers",
-                 "box_fp64_far", "sod_open_fp32"):
-        for first in (W4, W6, 1):
+                 "box_fp64_far", "sod_open_fp32", "box_periodic_fp64", "slit_fp64_vacuum",
+                 "thermal_couette_fp32"):
+        for first in (0, 1, 2, 3, 4, W4, W6):
             if first == W6 and name in XB_CASES:
                 continue
             out.append((name, first))
