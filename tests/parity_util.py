@@ -88,6 +88,10 @@ def compare_cells(pb, st_o, st_g, cells_ok, tol=1e-5):
     out = {}
     for name, b, sc in (("mom", 0, s_cen), ("raw", 1, s_raw), ("avg", 2, s_raw),
                         ("avgs", 3, s_raw)):
+        # a moment far above its natural scale (a degenerate cell: weights of
+        # either sign, a trace of K far below its diagonal) is compared
+        # relative to its own size
+        sc = np.maximum(sc, np.abs(co[:, 13 * b:13 * b + 13]))
         # empty cells have no scale (0 / 0); they are not in `use`, and a NaN
         # in a used cell fails the bar (the max is NaN)
         with np.errstate(invalid="ignore", divide="ignore"):
@@ -129,12 +133,17 @@ def compare_step(pb, st_o, st_g, dg_o, dg_g, f_o, f_g, report=None, excuse=None)
     oo, og = st_o.offsets, st_g.offsets
     th = pb.gas.R * 273.0
     sq = math.sqrt(th)
+    # positions: a few roundings of the larger of the domain size and the
+    # longest flight of the step (a flight of several domain lengths between
+    # walls carries the rounding of the distance flown)
+    vmax = float(np.abs(st_o.parts[:, 2:5]).max(initial=0.0)) * math.sqrt(3.0)
+    L = max(abs(pb.y1), abs(pb.x1 if pb.dim == 2 else 0), vmax * pb.dt)
     if pb.precision == 32:
-        tol_x = 4e-7 * max(abs(pb.y1), abs(pb.x1 if pb.dim == 2 else 0))
+        tol_x = 4e-7 * L
         tol_c = 2e-5 * sq
         tol_w = 2e-5
     else:
-        tol_x = 1e-12 * abs(pb.y1)
+        tol_x = 1e-12 * L
         tol_c = 1e-9 * sq
         tol_w = 1e-9
     worst = dict(x=0.0, c=0.0, w=0.0)
