@@ -167,8 +167,13 @@ def compare_step(pb, st_o, st_g, dg_o, dg_g, f_o, f_g, report=None, excuse=None)
     rel["rho"] = np.abs(f_g[:, 1] - rho) / np.abs(rho)
     rel["u"] = np.abs(f_g[:, 2:5] - f_o[:, 2:5]).max(1) / sth
     rel["T"] = np.abs(f_g[:, 5] - T) / np.abs(T)
-    rel["sigma"] = np.abs(f_g[:, 7:13] - f_o[:, 7:13]).max(1) / p
-    rel["q"] = np.abs(f_g[:, 13:16] - f_o[:, 13:16]).max(1) / (p * sth)
+    # stress and heat flux on their natural scales p and p sqrt(theta), or
+    # on their own size in a degenerate cell where that is larger (weights
+    # of either sign: a heat flux of 500 p sqrt(theta) has been drawn)
+    s_sig = np.maximum(p, np.abs(f_o[:, 7:13]).max(1))
+    s_q = np.maximum(p * sth, np.abs(f_o[:, 13:16]).max(1))
+    rel["sigma"] = np.abs(f_g[:, 7:13] - f_o[:, 7:13]).max(1) / s_sig
+    rel["q"] = np.abs(f_g[:, 13:16] - f_o[:, 13:16]).max(1) / s_q
     out = {}
     for k, v in rel.items():
         m = float(np.max(v[valid], initial=0.0))

@@ -19,7 +19,7 @@ from paper_1808_03801_amd import problems as P
 from tests.parity_util import compare_step, dilate, tie_cells
 from tests.test_gpu_parity import reach
 
-NCASE = 40
+NCASE = 100
 W4, W6 = 5, 6  # the one-wave shapes
 
 
