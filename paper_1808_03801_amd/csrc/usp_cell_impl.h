@@ -374,7 +374,7 @@ __device__ __forceinline__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& 
             while ((er + 1) * (er + 2) / 2 <= tid) ++er;
             es = tid - er * (er + 1) / 2;
         }
-        double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+        double acc = 0.0;
         bool mine = false;
         for (int q0 = 0; q0 < na; q0 += PSB) {
             wg_sync<NT>();
@@ -395,23 +395,18 @@ __device__ __forceinline__ int spawn_r(const InstDev& I, Parts<real, DIM, PPT>& 
             }
             wg_sync<NT>();
             if (tid < 20) {
-                // four running sums over q mod 4 (a fixed order: the loads of
-                // successive particles overlap), joined after the last chunk
+                // one running sum in batch order, chunk after chunk (the
+                // plain sum's order): an ill-conditioned Gram system (a batch
+                // of a few particles) then gives the weights of the plain
+                // sum, not weights off by its rounding times the condition
+                // number
                 const int nq = na - q0 < PSB ? na - q0 : PSB;
                 const int ea = tid < 15 ? er : 5, eb = tid < 15 ? es : tid - 15;
-                int q = 0;
-                for (; q + 4 <= nq; q += 4) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        acc4[u] += L.psb[6 * (q + u) + ea] * L.psb[6 * (q + u) + eb];
-                }
-#pragma unroll
-                for (int u = 0; u < 3; ++u)
-                    if (q + u < nq) acc4[u] += L.psb[6 * (q + u) + ea] * L.psb[6 * (q + u) + eb];
+                for (int q = 0; q < nq; ++q) acc += L.psb[6 * q + ea] * L.psb[6 * q + eb];
             }
         }
         wg_sync<NT>();
-        if (tid < 20) L.sc[tid] = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
+        if (tid < 20) L.sc[tid] = acc;
         wg_sync<NT>();
         // only the waves holding the batch solve and update
         if (__ballot(mine) == 0) return na;

@@ -29,6 +29,18 @@ def tie_cells(dg_oracle):
     return m < TIE
 
 
+def degenerate_cells(dg_oracle, f_oracle):
+    """cells the step leaves without valid moments: the oracle skipped their
+    relaxation (f-tilde^* of non-positive mass or temperature) or their
+    result has non-positive density or temperature.  Weights of either sign
+    cancel there, so a rounding of the state precision is amplified by the
+    ratio of sum |W| to |sum W| in every value the cell produces; their counts
+    and integer decisions are compared, their values are not."""
+    F_SKIP = 1
+    flags = dg_oracle[:, O.DIAG["flags"]].astype(np.int64)
+    return ((flags & F_SKIP) != 0) | ~(f_oracle[:, 1] > 0.0) | ~(f_oracle[:, 5] > 0.0)
+
+
 def dilate(pb, mask, k):
     """cells within k cells (each axis) of a cell of mask"""
     m = mask.reshape(pb.ny, pb.nx)
@@ -107,11 +119,15 @@ def compare_cells(pb, st_o, st_g, cells_ok, tol=1e-5):
     return out
 
 
-def compare_step(pb, st_o, st_g, dg_o, dg_g, f_o, f_g, report=None, excuse=None):
+def compare_step(pb, st_o, st_g, dg_o, dg_g, f_o, f_g, report=None, excuse=None,
+                 excuse_values=None):
     """Returns a dict of mismatch counts; raises AssertionError with details
     when the bar is not met.  excuse: cells whose integer decisions may
     differ for a reason outside this step (a tie of an earlier step in
-    reach of them)."""
+    reach of them); excuse_values: cells whose values may differ for such a
+    reason (a degenerate cell of an earlier step in reach of them).  Cells
+    with particles whose values the step leaves degenerate
+    (degenerate_cells) are compared on their integer decisions only."""
     nc = pb.ncell
     ties = tie_cells(dg_o)
     if excuse is not None:
@@ -129,6 +145,9 @@ def compare_step(pb, st_o, st_g, dg_o, dg_g, f_o, f_g, report=None, excuse=None)
                     for c in np.nonzero(unexplained)[0][:2] for k in INT_DIAG
                     if dg_o[c, O.DIAG[k]] != dg_g[c, O.DIAG[k]]))
     ok = ~bad_int
+    deg = degenerate_cells(dg_o, f_o) & (st_o.counts > 0)
+    if excuse_values is not None:
+        deg = deg | excuse_values
     # particles of matching cells, element by element
     oo, og = st_o.offsets, st_g.offsets
     th = pb.gas.R * 273.0
@@ -145,9 +164,12 @@ def compare_step(pb, st_o, st_g, dg_o, dg_g, f_o, f_g, report=None, excuse=None)
     else:
         tol_x = 1e-12 * L
         tol_c = 1e-9 * sq
-        tol_w = 1e-9
+        # a projected batch of a few particles solves a Gram system whose
+        # condition number (up to 1e10 by its pivot test) multiplies the
+        # rounding of its inputs
+        tol_w = 1e-6 if pb.spawn_projection == 1 else 1e-9
     worst = dict(x=0.0, c=0.0, w=0.0)
-    for c in np.nonzero(ok)[0]:
+    for c in np.nonzero(ok & ~deg)[0]:
         a = st_o.parts[oo[c]:oo[c + 1]]
         b = st_g.parts[og[c]:og[c + 1]]
         dx = np.abs(a[:, :2] - b[:, :2]).max(initial=0.0)
@@ -161,7 +183,7 @@ def compare_step(pb, st_o, st_g, dg_o, dg_g, f_o, f_g, report=None, excuse=None)
         assert dw <= tol_w, f"cell {c}: weight differs by {dw}"
     # moments per cell
     rho, T, p = f_o[:, 1], f_o[:, 5], f_o[:, 6]
-    valid = ok & (p > 0)
+    valid = ok & ~deg & (p > 0)
     sth = np.sqrt(np.where(valid, p / np.where(rho > 0, rho, 1.0), 1.0))
     rel = {}
     rel["rho"] = np.abs(f_g[:, 1] - rho) / np.abs(rho)
@@ -181,12 +203,13 @@ def compare_step(pb, st_o, st_g, dg_o, dg_g, f_o, f_g, report=None, excuse=None)
         assert m <= 1e-5, f"moment {k}: max relative error {m}"
     # P_ne and the averages: a cell's P_ne reads its neighbours' moments
     kk = 1
-    near_bad = dilate(pb, bad_int, kk)
+    near_bad = dilate(pb, bad_int | deg, kk)
     pne_rel = np.abs(f_g[:, 16] - f_o[:, 16])
     out["pne_field"] = float(np.max(pne_rel[~near_bad], initial=0.0))
     assert out["pne_field"] <= 1e-5, f"P_ne: max difference {out['pne_field']}"
     out.update(compare_cells(pb, st_o, st_g, ~near_bad))
-    out.update(mismatched_cells=int(bad_int.sum()), tie_cells=int(ties.sum()), **worst)
+    out.update(mismatched_cells=int(bad_int.sum()), tie_cells=int(ties.sum()),
+               degenerate_cells=int(deg.sum()), **worst)
     if report is not None:
         report.update(out)
     return out

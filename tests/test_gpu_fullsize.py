@@ -11,7 +11,7 @@ import pytest
 import bench
 from oracle import oracle as O
 from paper_1808_03801_amd import problems as P
-from tests.parity_util import compare_step, dilate, tie_cells
+from tests.parity_util import compare_step, degenerate_cells, dilate, tie_cells
 from tests.test_gpu_parity import reach
 
 
@@ -42,16 +42,18 @@ def _parity(pbs, warm=2, graph=True, steps=1):
         for pb, g, st in zip(pbs, gs, sts):
             o = O.Oracle(pb)
             o.set_state(st)
-            excuse = None
+            excuse = excuse_values = None
             if steps == 2:
                 o.step(1)
-                excuse = dilate(pb, tie_cells(o.diag()), reach(pb, o.get_state()))
+                r = reach(pb, o.get_state())
+                excuse = dilate(pb, tie_cells(o.diag()), r)
+                excuse_values = dilate(pb, degenerate_cells(o.diag(), o.fields(0)), r)
                 o.step(1)
             else:
                 o.step(steps)
             rep = {}
             compare_step(pb, o.get_state(), g.get_state(), o.diag(), g.diag(), o.fields(0),
-                         g.fields(0), report=rep, excuse=excuse)
+                         g.fields(0), report=rep, excuse=excuse, excuse_values=excuse_values)
             print(pb.name, pb.ncell, "cells", int(st.counts.sum()), "particles", steps,
                   "steps", rep)
     finally:

@@ -11,7 +11,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1808_03801_amd import problems as P
-from tests.parity_util import compare_step, dilate, tie_cells
+from tests.parity_util import compare_step, degenerate_cells, dilate, tie_cells
 from tests.philox_ref import philox4
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -202,13 +202,15 @@ def two_step_parity(ctx, pb, st, name=""):
         g.set_diag(True)
         g.set_state(st)
         o.step(1)
-        excuse = dilate(pb, tie_cells(o.diag()), reach(pb, o.get_state()))
+        r = reach(pb, o.get_state())
+        excuse = dilate(pb, tie_cells(o.diag()), r)
+        excuse_values = dilate(pb, degenerate_cells(o.diag(), o.fields(0)), r)
         o.step(1)
         g.step(2)
         ctx.sync()
         rep = {}
         compare_step(pb, o.get_state(), g.get_state(), o.diag(), g.diag(), o.fields(0),
-                     g.fields(0), report=rep, excuse=excuse)
+                     g.fields(0), report=rep, excuse=excuse, excuse_values=excuse_values)
         print(name, "two steps", rep)
         return rep
     finally:

@@ -16,10 +16,10 @@ import pytest
 
 from oracle import oracle as O
 from paper_1808_03801_amd import problems as P
-from tests.parity_util import compare_step, dilate, tie_cells
+from tests.parity_util import compare_step, degenerate_cells, dilate, tie_cells
 from tests.test_gpu_parity import reach
 
-NCASE = 100
+NCASE = 300
 W4, W6 = 5, 6  # the one-wave shapes
 
 
@@ -137,17 +137,19 @@ def _run(ctx, pb, first, st, nsteps):
             g.set_shape(first)
         g.set_diag(True)
         g.set_state(st)
-        excuse = None
+        excuse = excuse_values = None
         if nsteps == 2:
             o.step(1)
-            excuse = dilate(pb, tie_cells(o.diag()), reach(pb, o.get_state()))
+            r = reach(pb, o.get_state())
+            excuse = dilate(pb, tie_cells(o.diag()), r)
+            excuse_values = dilate(pb, degenerate_cells(o.diag(), o.fields(0)), r)
         o.step(1)
         assert o.error == 0
         g.step(nsteps)
         ctx.sync()
         rep = {}
         compare_step(pb, o.get_state(), g.get_state(), o.diag(), g.diag(), o.fields(0),
-                     g.fields(0), report=rep, excuse=excuse)
+                     g.fields(0), report=rep, excuse=excuse, excuse_values=excuse_values)
         return rep
     finally:
         g.free()
