@@ -171,3 +171,45 @@ def test_random_workload_parity(ctx, k):
     assert st is not None, label
     print(label, "first shape", first, "one step", _run(ctx, pb, first, st, 1), flush=True)
     print(label, "two steps", _run(ctx, pb, first, st, 2), flush=True)
+
+
+NBATCH, PER_BATCH = 12, 6
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("b", range(NBATCH))
+def test_random_batches_parity(ctx, b):
+    """draws stepped together in one call (mixed precisions, dimensions,
+    boundary variants and first shapes share the launches of each pass):
+    each instance against the oracle, two steps through the fused pass"""
+    ks = [(b * PER_BATCH + j * 37) % NCASE for j in range(PER_BATCH)]
+    cases = [draw_case(k) for k in ks]
+    runs = []
+    try:
+        for label, pb, first, warm in cases:
+            st = _oracle_state(pb, warm)
+            assert st is not None, label
+            g = ctx.add(pb)
+            if first >= 0:
+                g.set_shape(min(first, g.shape()[1]) if first < W4 else first)
+            g.set_diag(True)
+            g.set_state(st)
+            runs.append((label, pb, st, g))
+        ctx.step([r[3] for r in runs], 2)
+        ctx.sync()
+        for label, pb, st, g in runs:
+            o = O.Oracle(pb)
+            o.set_state(st)
+            o.step(1)
+            r = reach(pb, o.get_state())
+            excuse = dilate(pb, tie_cells(o.diag()), r)
+            excuse_values = dilate(pb, degenerate_cells(o.diag(), o.fields(0)), r)
+            o.step(1)
+            assert o.error == 0
+            rep = {}
+            compare_step(pb, o.get_state(), g.get_state(), o.diag(), g.diag(), o.fields(0),
+                         g.fields(0), report=rep, excuse=excuse, excuse_values=excuse_values)
+            print(label, "in batch", b, rep, flush=True)
+    finally:
+        for run in runs:
+            run[3].free()
