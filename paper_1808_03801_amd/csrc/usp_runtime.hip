@@ -269,6 +269,10 @@ usp_status validate(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb, con
         return fail(ctx, USP_EINVAL, "max_ppc must be in [2, 2048]");
     if (nm->n_avg < 1) return fail(ctx, USP_EINVAL, "n_avg must be >= 1");
     if ((long long)pb->nx * pb->ny > (1LL << 26)) return fail(ctx, USP_EINVAL, "too many cells");
+    // the gather addresses a particle slot of the instance by 31 bits (the
+    // top bit marks the far-mover list)
+    if ((long long)pb->nx * pb->ny * ((nm->max_ppc + 63) / 64 * 64) >= (1LL << 31))
+        return fail(ctx, USP_EINVAL, "cells x capacity must stay below 2^31 particle slots");
     bool open = false;
     for (int f = 0; f < 4; ++f) {
         const usp_face& fc = pb->face[f];

@@ -308,6 +308,17 @@ def test_mode_switches_outside_their_values_are_refused(ctx):
 
 
 @pytest.mark.gpu
+def test_an_instance_beyond_31_bit_slot_addresses_is_refused(ctx):
+    """cells x capacity of 2^31 slots or more is refused before any
+    allocation (the gather addresses a slot by 31 bits)"""
+    usp = _gpu()
+    pb = P.homogeneous_box(ncell=1 << 21, ppc=8, precision=32, seed=1).replace(max_ppc=1024)
+    with pytest.raises(usp.UspError) as e:
+        ctx.add(pb)
+    assert e.value.status == -1 and "2^31" in str(e.value)
+
+
+@pytest.mark.gpu
 def test_an_instance_listed_twice_in_one_step_is_refused(ctx):
     """two workgroups on the same cells would race: refused before any launch"""
     usp = _gpu()
