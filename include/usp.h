@@ -199,8 +199,10 @@ usp_status usp_footprint(const usp_problem* pb, const usp_numerics* nm, size_t* 
  * cell's (u, T), weight 1; then the moments of f^0 and P_ne^0.  init_n [ncell]
  * (1/m^3), init_u [ncell][3] (m/s), init_T [ncell] (K) are host arrays.
  * Refused with USP_EINVAL: an invalid argument or mode value, more than 2^26
- * cells, or cells x capacity (max_ppc rounded up to 64) of 2^31 particle
- * slots or more (a slot of the instance is addressed by 31 bits). */
+ * cells, cells x capacity (max_ppc rounded up to 64) of 2^31 particle slots
+ * or more (a slot of the instance is addressed by 31 bits), or an open face
+ * whose reservoir would bring more than max_ppc particles into a boundary
+ * cell per step on average (n sqrt(kB T / (2 pi m)) area dt / Np). */
 usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb,
                              const usp_numerics* nm, const double* init_n,
                              const double* init_u, const double* init_T, int* id_out);

@@ -284,6 +284,22 @@ usp_status validate(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb, con
             return fail(ctx, USP_EINVAL, "open face needs n, n_b >= 0 and T, T_b > 0");
         if (fc.u[f / 2] != 0.0)
             return fail(ctx, USP_EINVAL, "open face reservoir moves across the face");
+        // expected entering particles per cell and step, n sqrt(kT / (2 pi m))
+        // area dt / Np, for both reservoir states: beyond max_ppc every
+        // boundary cell would overflow at once (and a count beyond an int
+        // would wrap)
+        if (pb->dim == 1 && f < 2) continue;
+        const double area = pb->dim == 2 ? (f < 2 ? pb->dy : pb->dx) : 1.0;
+        for (int b = 0; b < 2; ++b) {
+            // the second state only on a split face of a 2-D problem
+            if (b == 1 && !(pb->dim == 2 && fc.split < HUGE_VAL)) continue;
+            const double n = b ? fc.n_b : fc.n, T = b ? fc.T_b : fc.T;
+            const double v = n * sqrt(gas->kB * T / (gas->m * 2.0 * M_PI)) * area * nm->dt / nm->Np;
+            if (!(v <= (double)nm->max_ppc))
+                return fail(ctx, USP_EINVAL,
+                            "an open face would bring more than max_ppc particles into a cell "
+                            "per step");
+        }
     }
     if ((pb->face[0].kind == USP_BC_PERIODIC) != (pb->face[1].kind == USP_BC_PERIODIC) ||
         (pb->face[2].kind == USP_BC_PERIODIC) != (pb->face[3].kind == USP_BC_PERIODIC))

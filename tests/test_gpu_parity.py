@@ -319,6 +319,22 @@ def test_an_instance_beyond_31_bit_slot_addresses_is_refused(ctx):
 
 
 @pytest.mark.gpu
+def test_an_open_face_flooding_its_cells_is_refused(ctx):
+    """a reservoir that would bring more than max_ppc particles into a
+    boundary cell per step is refused at creation (every such cell would
+    overflow in the first step); the same channel with a dilute reservoir
+    is accepted"""
+    usp = _gpu()
+    good = P.open_channel_1d(Kn=0.1, ncell=30, ppc=100, n_hi=1.0, seed=15)
+    g = ctx.add(good)
+    g.free()
+    bad = P.open_channel_1d(Kn=0.1, ncell=30, ppc=100, n_hi=1.0e4, seed=15)
+    with pytest.raises(usp.UspError) as e:
+        ctx.add(bad)
+    assert e.value.status == -1 and "open face" in str(e.value)
+
+
+@pytest.mark.gpu
 def test_an_instance_listed_twice_in_one_step_is_refused(ctx):
     """two workgroups on the same cells would race: refused before any launch"""
     usp = _gpu()
