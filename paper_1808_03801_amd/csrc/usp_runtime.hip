@@ -242,15 +242,20 @@ Window choose_window(const usp_gas* gas, const usp_problem* pb, const usp_numeri
     vmax *= 1.3;
     Window w;
     const bool px = pb->face[0].kind == USP_BC_PERIODIC, py = pb->face[2].kind == USP_BC_PERIODIC;
+    // cells crossed in one step at vmax, held below the axis limit before it
+    // becomes an int (a speed far beyond the grid must not wrap the count)
+    auto reach_cells = [&](double inv_d, int limit) {
+        const double k = ceil(vmax * nm->dt * inv_d) + 1.0;
+        return k < (double)limit ? (int)k : limit;
+    };
     if (pb->dim == 1) {
-        int k = nm->window > 0 ? nm->window : (int)ceil(vmax * nm->dt * pb->inv_dy) + 1;
-        w.Ky = std::min(k, axis_limit(pb->ny, py, 127));
+        const int lim = axis_limit(pb->ny, py, 127);
+        w.Ky = nm->window > 0 ? std::min(nm->window, lim) : reach_cells(pb->inv_dy, lim);
         w.Kx = 0;
     } else {
-        int kx = nm->window > 0 ? nm->window : (int)ceil(vmax * nm->dt * pb->inv_dx) + 1;
-        int ky = nm->window > 0 ? nm->window : (int)ceil(vmax * nm->dt * pb->inv_dy) + 1;
-        w.Kx = std::min(kx, axis_limit(pb->nx, px, 7));
-        w.Ky = std::min(ky, axis_limit(pb->ny, py, 7));
+        const int limx = axis_limit(pb->nx, px, 7), limy = axis_limit(pb->ny, py, 7);
+        w.Kx = nm->window > 0 ? std::min(nm->window, limx) : reach_cells(pb->inv_dx, limx);
+        w.Ky = nm->window > 0 ? std::min(nm->window, limy) : reach_cells(pb->inv_dy, limy);
     }
     return w;
 }
