@@ -202,7 +202,9 @@ usp_status usp_footprint(const usp_problem* pb, const usp_numerics* nm, size_t* 
  * cells, cells x capacity (max_ppc rounded up to 64) of 2^31 particle slots
  * or more (a slot of the instance is addressed by 31 bits), or an open face
  * whose reservoir would bring more than max_ppc particles into a boundary
- * cell per step on average (n sqrt(kB T / (2 pi m)) area dt / Np). */
+ * cell per step on average (n sqrt(kB T / (2 pi m)) area dt / Np), or an
+ * initial field that is not finite, a negative density or temperature.  A
+ * cell whose initial count exceeds max_ppc sets the sticky USP_ECAPACITY. */
 usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem* pb,
                              const usp_numerics* nm, const double* init_n,
                              const double* init_u, const double* init_T, int* id_out);

@@ -657,6 +657,18 @@ usp_status usp_instance_init(usp_ctx* ctx, const usp_gas* gas, const usp_problem
     usp_status s = validate(ctx, gas, pb, nm);
     if (s) return s;
     if (!init_n || !init_u || !init_T || !id_out) return fail(ctx, USP_EINVAL, "null init field");
+    // the initial state: a finite, non-negative particle count (n V / Np, the
+    // device rounds it), temperature and velocity in every cell
+    for (long long c = 0; c < (long long)pb->nx * pb->ny; ++c) {
+        const double v = init_n[c] * pb->vcell / nm->Np;
+        if (!(v >= 0.0 && v < 1.0e9))
+            return fail(ctx, USP_EINVAL, "init_n must give a finite, non-negative count per cell");
+        if (!(init_T[c] >= 0.0 && init_T[c] < HUGE_VAL))
+            return fail(ctx, USP_EINVAL, "init_T must be finite and non-negative");
+        for (int k = 0; k < 3; ++k)
+            if (!(fabs(init_u[3 * c + k]) < HUGE_VAL))
+                return fail(ctx, USP_EINVAL, "init_u must be finite");
+    }
     HIPCHK(ctx, hipSetDevice(ctx->dev.device));
     Instance* in = new Instance();
     InstDev& h = in->h;

@@ -335,6 +335,22 @@ def test_an_open_face_flooding_its_cells_is_refused(ctx):
 
 
 @pytest.mark.gpu
+def test_an_invalid_initial_field_is_refused(ctx):
+    """a negative or non-finite density, temperature or velocity in any cell
+    is refused at creation"""
+    usp = _gpu()
+    pb = _cases()["thermal_couette_fp32"]()
+    for field, idx, bad in (("init_n", 7, -1.0), ("init_n", 0, math.nan),
+                            ("init_T", 3, -5.0), ("init_T", 3, math.inf),
+                            ("init_u", (5, 1), math.nan)):
+        arr = getattr(pb, field).copy()
+        arr[idx] = bad
+        with pytest.raises(usp.UspError) as e:
+            ctx.add(pb.replace(**{field: arr}))
+        assert e.value.status == -1, (field, bad)
+
+
+@pytest.mark.gpu
 def test_an_instance_listed_twice_in_one_step_is_refused(ctx):
     """two workgroups on the same cells would race: refused before any launch"""
     usp = _gpu()
