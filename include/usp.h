@@ -251,7 +251,9 @@ usp_status usp_num_particles(usp_ctx* ctx, int id, long long* n);
  * [ncell][54] = centred moments (S0, u[3], K[6], Q[3]), raw sums (S0, S1[3],
  * S2[6], S3[3]), time-averaged raw sums of f^n, of f-tilde^*, P_ne^n,
  * P_ne^{n-1}.  get: parts may be NULL (counts only).  set: cells may be NULL
- * (moments recomputed, averages cleared, P_ne from the fields). */
+ * (moments recomputed, averages cleared, P_ne from the fields); step and
+ * n_samples must be non-negative (USP_EINVAL) and every count within
+ * [0, max_ppc] (USP_ECAPACITY). */
 usp_status usp_get_state(usp_ctx* ctx, int id, int* counts, double* parts, double* cells,
                          int* step, int* n_samples);
 usp_status usp_set_state(usp_ctx* ctx, int id, const int* counts, const double* parts,

@@ -1318,6 +1318,8 @@ usp_status usp_set_state(usp_ctx* ctx, int id, const int* counts, const double* 
 {
     Instance* in = get_inst(ctx, id);
     if (!in || !counts || !parts) return fail(ctx, USP_EINVAL, "bad set_state arguments");
+    if (step < 0 || n_samples < 0)
+        return fail(ctx, USP_EINVAL, "step and n_samples must be non-negative");
     const InstDev& h = in->h;
     in->sort_ok = false;
     int ctl[CTL_N];
