@@ -367,8 +367,8 @@ def main():
                     help="only run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the design notes for how the step would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the design notes describe how the step would shard)", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:
