@@ -53,7 +53,8 @@ def _parity(pbs, warm=2, graph=True, steps=1):
                 o.step(steps)
             rep = {}
             compare_step(pb, o.get_state(), g.get_state(), o.diag(), g.diag(), o.fields(0),
-                         g.fields(0), report=rep, excuse=excuse, excuse_values=excuse_values)
+                         g.fields(0), report=rep, excuse=excuse, excuse_values=excuse_values,
+                         steps=steps)
             print(pb.name, pb.ncell, "cells", int(st.counts.sum()), "particles", steps,
                   "steps", rep)
     finally:

@@ -210,7 +210,8 @@ def two_step_parity(ctx, pb, st, name=""):
         ctx.sync()
         rep = {}
         compare_step(pb, o.get_state(), g.get_state(), o.diag(), g.diag(), o.fields(0),
-                     g.fields(0), report=rep, excuse=excuse, excuse_values=excuse_values)
+                     g.fields(0), report=rep, excuse=excuse, excuse_values=excuse_values,
+                     steps=2)
         print(name, "two steps", rep)
         return rep
     finally:

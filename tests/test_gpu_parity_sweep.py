@@ -149,7 +149,8 @@ def _run(ctx, pb, first, st, nsteps):
         ctx.sync()
         rep = {}
         compare_step(pb, o.get_state(), g.get_state(), o.diag(), g.diag(), o.fields(0),
-                     g.fields(0), report=rep, excuse=excuse, excuse_values=excuse_values)
+                     g.fields(0), report=rep, excuse=excuse, excuse_values=excuse_values,
+                     steps=nsteps)
         return rep
     finally:
         g.free()
@@ -208,7 +209,8 @@ def test_random_batches_parity(ctx, b):
             assert o.error == 0
             rep = {}
             compare_step(pb, o.get_state(), g.get_state(), o.diag(), g.diag(), o.fields(0),
-                         g.fields(0), report=rep, excuse=excuse, excuse_values=excuse_values)
+                         g.fields(0), report=rep, excuse=excuse, excuse_values=excuse_values,
+                         steps=2)
             print(label, "in batch", b, rep, flush=True)
     finally:
         for run in runs:
