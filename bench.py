@@ -92,6 +92,17 @@ def _profile_figure(workload, key):
     return float(m.group(1))
 
 
+def regime_of(valu_frac, traffic_frac):
+    """the regime, from the measured fractions of peak: the larger of VALU
+    issue and measured HBM traffic (the algorithmic bytes are the roofline's
+    floor, not a measurement of what the kernel moves)"""
+    if valu_frac is not None and (traffic_frac is None or valu_frac >= traffic_frac):
+        return "VALU issue and per-cell latency"
+    if traffic_frac is not None:
+        return "HBM traffic"
+    return "unmeasured"
+
+
 def copy_calibration():
     """a plain device copy of known size (256 MiB, three times), so that the
     FETCH_SIZE / WRITE_SIZE counters can be scaled to bytes"""
@@ -286,16 +297,9 @@ def measure(name, steps, warmup, chunk, graph, tune):
     }
     r = out["roofline"]
     v = out["valu_issue"]
-    # the regime, from the measured fractions: the larger of VALU issue and
-    # measured HBM traffic (the algorithmic bytes are the roofline's floor)
     vf = None if v is None else v["frac"]
     tf = r["traffic_frac"]
-    if vf is not None and (tf is None or vf >= tf):
-        regime = "VALU issue and per-cell latency"
-    elif tf is not None:
-        regime = "HBM traffic"
-    else:
-        regime = "unmeasured"
+    regime = regime_of(vf, tf)
     r["regime"] = regime
     r["limiter"] = ("%s: VALU issue %s of peak, HBM %.1f %% of peak at the algorithmic "
                     "bytes and %s at the measured traffic"
