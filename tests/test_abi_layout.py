@@ -1,7 +1,8 @@
 """CPU: the binding's ctypes structures have the fields of include/usp.h's
 structs, in the same order and with the same sizes, so that a field added
 on one side only (a new numerics switch, say) fails here rather than
-shifting every later field the library reads."""
+shifting every later field the library reads; the same for the oracle's
+configuration record and its binding."""
 import ctypes as C
 import os
 import re
@@ -16,9 +17,9 @@ C_SIZES = {"double": 8, "int": 4, "uint64_t": 8, "long long": 8, "size_t": 8,
            "uint32_t": 4, "int32_t": 4}
 
 
-def _c_structs():
+def _c_structs(header=os.path.join("include", "usp.h")):
     """name -> [(field, bytes)] of every `typedef struct { ... } name;`"""
-    text = open(os.path.join(ROOT, "include", "usp.h")).read()
+    text = open(os.path.join(ROOT, header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     text = re.sub(r"//[^\n]*", "", text)
     out = {}
@@ -67,3 +68,10 @@ def test_ctypes_struct_matches_header(cname, ctype):
     cf = [(n, dict(pf).get(n) if b is None else b) for n, b in cf]
     assert [n for n, _ in cf] == [n for n, _ in pf], (cname, cf, pf)
     assert cf == pf, (cname, cf, pf)
+
+
+def test_oracle_config_matches_its_header():
+    from oracle import oracle as O
+    cf = _c_structs(os.path.join("oracle", "usp_oracle.h"))["uspo_config"]
+    pf = [(f[0], C.sizeof(f[1])) for f in O.Config._fields_]
+    assert cf == pf, (cf, pf)
