@@ -75,3 +75,20 @@ def test_oracle_config_matches_its_header():
     cf = _c_structs(os.path.join("oracle", "usp_oracle.h"))["uspo_config"]
     pf = [(f[0], C.sizeof(f[1])) for f in O.Config._fields_]
     assert cf == pf, (cf, pf)
+
+
+def test_footprint_counts_the_particle_buffers():
+    """usp_footprint (host arithmetic, no device): the two particle buffers
+    of (dim + 4) components per slot dominate, and the figure grows with the
+    cells, the capacity and the state precision"""
+    from paper_1808_03801_amd import problems as P
+    if not os.path.exists(usp.LIB_PATH):
+        pytest.skip("libusp.so not built")
+    pb = P.cavity_2d(Kn=0.01, n=32, ppc=100, seed=1)
+    cap = (pb.max_ppc + 63) // 64 * 64
+    parts = 2 * (pb.dim + 4) * pb.ncell * cap * 4
+    f = usp.footprint(pb)
+    assert parts <= f <= 1.5 * parts
+    assert usp.footprint(pb.replace(precision=64)) > 1.9 * parts
+    assert usp.footprint(pb.replace(max_ppc=2 * pb.max_ppc)) > 1.9 * parts
+    assert usp.footprint(P.cavity_2d(Kn=0.01, n=64, ppc=100, seed=1)) > 3.9 * parts
