@@ -386,9 +386,29 @@ usp_status with_kernel(int prec, int dim, F f)
     return f((double*)nullptr, std::integral_constant<int, 2>());
 }
 
+// the shapes with a built kernel; anything else has none (a launch of
+// another kernel with this shape's block and LDS sizes would run it outside
+// what it assumes)
+constexpr bool shape_is_built(Shape sh)
+{
+    if (sh.nt == 64) return sh.ppt2 == 0 && (sh.ppt == 4 || sh.ppt == 6);
+    if (sh.nt != 256) return false;
+    if (sh.ppt2 == 6) return sh.ppt == 4;
+    return sh.ppt2 == 0 && (sh.ppt == 1 || sh.ppt == 2 || sh.ppt == 4 || sh.ppt == 8);
+}
+
+constexpr bool all_shapes_built()
+{
+    for (int i = 0; i < NSHAPE; ++i)
+        if (!shape_is_built(SHAPES[i])) return false;
+    return true;
+}
+static_assert(all_shapes_built(), "every launch shape of the table needs its kernel");
+
 template <typename real, int D, bool XB>
 const void* cell_kernel_for(Shape sh)
 {
+    if (!shape_is_built(sh)) return nullptr;
     if (sh.nt == 64) {
         if (sh.ppt == 4) return (const void*)cell_kernel<real, D, 64, 4, 0, XB>;
         if constexpr (!XB) return (const void*)cell_kernel<real, D, 64, 6, 0, false>;
@@ -399,7 +419,8 @@ const void* cell_kernel_for(Shape sh)
         case 1: return (const void*)cell_kernel<real, D, 256, 1, 0, XB>;
         case 2: return (const void*)cell_kernel<real, D, 256, 2, 0, XB>;
         case 4: return (const void*)cell_kernel<real, D, 256, 4, 0, XB>;
-        default: return (const void*)cell_kernel<real, D, 256, 8, 0, XB>;
+        case 8: return (const void*)cell_kernel<real, D, 256, 8, 0, XB>;
+        default: return nullptr;
     }
 }
 
