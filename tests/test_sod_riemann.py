@@ -184,10 +184,12 @@ def test_oracle_sod_table4_case2_coarsest_grid():
 # ---- the GPU ------------------------------------------------------------
 
 def _gpu_ensemble(build, seeds, min_ok=None):
-    """mean fields at t_final over the seeds whose run finished.  At a few
-    hundred particles per cell (the paper used 2.5e4-2e5) an occasional run
-    grows a particle weight of thousands and then overflows a cell (the
-    oracle does the same for the same seed); min_ok runs must finish."""
+    """mean fields at t_final over the seeds whose run finished (min_ok of
+    them at least; all by default).  With the consistent added-particle
+    weights at a few hundred particles per cell (the paper used 2.5e4-2e5)
+    an occasional run grows a particle weight of thousands and then
+    overflows a cell (the oracle does the same for the same seed); the
+    Table 4 runs take the printed weights, with which every run finishes."""
     from paper_1808_03801_amd import usp
     ctx = usp.Context(0)
     try:
@@ -228,7 +230,7 @@ def test_gpu_sod_table4_case2_against_the_riemann_fan(row):
     which faulted the device in the 8-slot kernel of the open-face variant,
     is not run: that shape is switched off until the cause is found."""
     pb, f, t = _gpu_ensemble(lambda s: P.sod_table4(2, row, seed=400 + s, open_ends=False),
-                             range(8), min_ok=6)
+                             range(8))
     _check(_measure(pb, f, t), p_tol=0.04, u_tol=0.06, l1_tol=0.04)
 
 
@@ -242,7 +244,7 @@ def test_gpu_sod_table4_case1_time_steps_agree():
     res = {}
     for row in range(3):
         pb, f, t = _gpu_ensemble(lambda s: P.sod_table4(1, row, seed=500 + s, open_ends=False),
-                                 range(8), min_ok=6)
+                                 range(8))
         res[row] = (pb, f, t)
     pb0, f0, t0 = res[0]
     (rl, _, pl), _ = _states(pb0)
