@@ -224,10 +224,13 @@ def compare_step(pb, st_o, st_g, dg_o, dg_g, f_o, f_g, report=None, excuse=None,
     # stress and heat flux on their natural scales p and p sqrt(theta), or
     # on their own size in a degenerate cell where that is larger (weights
     # of either sign: a heat flux of 500 p sqrt(theta) has been drawn)
+    # (an empty cell has both scales 0; only valid cells, where they are
+    # positive, are read below, and a NaN there fails the bar)
     s_sig = np.maximum(p, np.abs(f_o[:, 7:13]).max(1))
     s_q = np.maximum(p * sth, np.abs(f_o[:, 13:16]).max(1))
-    rel["sigma"] = np.abs(f_g[:, 7:13] - f_o[:, 7:13]).max(1) / s_sig
-    rel["q"] = np.abs(f_g[:, 13:16] - f_o[:, 13:16]).max(1) / s_q
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rel["sigma"] = np.abs(f_g[:, 7:13] - f_o[:, 7:13]).max(1) / s_sig
+        rel["q"] = np.abs(f_g[:, 13:16] - f_o[:, 13:16]).max(1) / s_q
     out = {}
     for k, v in rel.items():
         m = float(np.max(v[valid], initial=0.0))
