@@ -372,7 +372,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
-              "(the design notes describe how the step would shard)", file=sys.stderr)
+              "(the step would shard by cell slabs or tiles per GPU, exchanging the "
+              "particles that cross a shard boundary each step)", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:

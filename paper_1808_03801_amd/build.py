@@ -11,7 +11,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
          # no implicit FMA contraction: results must not depend on which
          # kernel instantiation (particles per thread) ran a cell
          "-ffp-contract=off",
-         # packed FP32 instructions stay off (see the design notes)
+         # packed FP32 instructions stay off: some of their forms have given
+         # wrong results on this chip, with no error
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]
 
