@@ -177,15 +177,19 @@ def compare_step(pb, st_o, st_g, dg_o, dg_g, f_o, f_g, report=None, excuse=None,
     sq = math.sqrt(th)
     # positions: a few roundings of the larger of the domain size and the
     # longest flight of the step (a flight of several domain lengths between
-    # walls carries the rounding of the distance flown)
+    # walls carries the rounding of the distance flown); over several steps
+    # also the velocity difference an earlier relaxation left (within the
+    # velocity bar, on the larger of sqrt(theta) and the particle's speed),
+    # flown for dt in each later step
     vmax = float(np.abs(st_o.parts[:, 2:5]).max(initial=0.0)) * math.sqrt(3.0)
     L = max(abs(pb.y1), abs(pb.x1 if pb.dim == 2 else 0), vmax * pb.dt)
+    flown = (steps - 1) * max(sq, vmax) * pb.dt
     if pb.precision == 32:
-        tol_x = 4e-7 * L
+        tol_x = 4e-7 * L + 2e-5 * flown
         tol_c = 2e-5 * sq * steps
         tol_w = 2e-5 * steps
     else:
-        tol_x = 1e-12 * L
+        tol_x = 1e-12 * L + 1e-9 * flown
         tol_c = 1e-9 * sq * steps
         # a projected batch of a few particles solves a Gram system whose
         # condition number (up to 1e10 by its pivot test) multiplies the
