@@ -25,7 +25,11 @@ NDIAG = 32
 DIAG = dict(n_in=0, n4=1, n_sel=2, n_usp=3, n_del=4, n7=5, n_out=6, n2=7, s_sel=8, p_sel=9,
             flags=10, chol_fb=11, M0=12, P0x=13, P0y=14, P0z=15, E0=16, M1=17, P1x=18, P1y=19,
             P1z=20, E1=21, clamp=22, marg_sel=23, marg_round=24, marg_cnt=25, Wr=26, s2=27,
-            marg_cnt2=28, n_inj=29, n_gone=30)
+            marg_cnt2=28, n_inj=29, n_gone=30, marg_face=31)
+# marg_face: the smallest distance (m) of a landing point of the step's
+# flights to a face this cell shares with another (interior or periodic),
+# kept in both cells of that face; the rounding of a flight that ends there
+# decides which of the two receives the particle
 
 
 class Config(C.Structure):

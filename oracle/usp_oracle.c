@@ -161,7 +161,8 @@ static void pl_push(plist* l, part q)
 enum {
     D_NIN = 0, D_N4, D_NSEL, D_NUSP, D_NDEL, D_N7, D_NOUT, D_N2, D_SSEL, D_PSEL, D_FLAGS,
     D_CHOLFB, D_M0, D_P0X, D_P0Y, D_P0Z, D_E0, D_M1, D_P1X, D_P1Y, D_P1Z, D_E1, D_CLAMP,
-    D_MARG_SEL, D_MARG_ROUND, D_MARG_CNT, D_WR, D_S2, D_MARG_CNT2, D_NINJ, D_NGONE
+    D_MARG_SEL, D_MARG_ROUND, D_MARG_CNT, D_WR, D_S2, D_MARG_CNT2, D_NINJ, D_NGONE,
+    D_MARG_FACE
 };
 enum { F_SKIP = 1, F_FAILMASS = 2, F_FAILENERGY = 4, F_NOUSP = 8, F_WHOLE = 16 };
 
@@ -463,6 +464,42 @@ static int spawn(const uspo* o, int batch, int cell, const cellf* f, double pne,
 /* ------------------------------------------------------------------------ */
 /* Step 3: advection and walls                                               */
 /* ------------------------------------------------------------------------ */
+
+/* Where a flight ends next to a face that two cells share (an interior
+ * face, or a periodic pair), its rounding decides which of them receives
+ * the particle.  Keeps, in both cells, the smallest distance of a landing
+ * point in cell d to such a face (test diagnostics only: the step does not
+ * read it).  Walls are not such faces: a landing point at a wall stays in
+ * its cell. */
+static void note_face_margin(const uspo_config* g, double* diag, int d, const part* q)
+{
+    int ix = d % g->nx, iy = d / g->nx;
+    double best = INFINITY;
+    int other = -1;
+    for (int a = g->dim == 2 ? 0 : 1; a < 2; ++a) {
+        double pos = a == 0 ? q->x : q->y, org = a == 0 ? g->x0 : g->y0;
+        double h = a == 0 ? g->dx : g->dy;
+        int i = a == 0 ? ix : iy, n = a == 0 ? g->nx : g->ny;
+        int periodic = g->face_kind[2 * a] == 2;
+        for (int sd = 0; sd < 2; ++sd) {
+            int j = i + (sd ? 1 : -1);
+            if (j < 0 || j >= n) {
+                if (!periodic || n == 1) continue;
+                j = (j + n) % n;
+            }
+            double dist = fabs(pos - (org + (i + sd) * h));
+            if (dist < best) {
+                best = dist;
+                other = a == 0 ? iy * g->nx + j : j * g->nx + ix;
+            }
+        }
+    }
+    if (other < 0) return;
+    double* m0 = diag + (size_t)USPO_NDIAG * d + D_MARG_FACE;
+    double* m1 = diag + (size_t)USPO_NDIAG * other + D_MARG_FACE;
+    if (best < *m0) *m0 = best;
+    if (best < *m1) *m1 = best;
+}
 
 static int cell_of(const uspo_config* g, double x, double y)
 {
@@ -1432,6 +1469,7 @@ static void one_step(uspo* o)
      * (after those present, faces in index order), then the stable sort by
      * new cell; particles leaving through open faces are dropped */
     long long total = 0;
+    for (int c = 0; c < nc; ++c) o->diag[(size_t)USPO_NDIAG * c + D_MARG_FACE] = INFINITY;
     int* ninj = (int*)calloc((size_t)nc * 4, sizeof(int));
     for (int c = 0; c < nc; ++c) {
         int t = 0;
@@ -1461,6 +1499,7 @@ static void one_step(uspo* o)
                 ++gone;
                 continue;
             }
+            note_face_margin(g, o->diag, dcell, &q);
             int sx = c % g->nx, sy = c / g->nx, dx = dcell % g->nx, dy = dcell / g->nx;
             e[k].dest = dcell;
             e[k].dy = min_image(sy - dy, g->ny, pery);
