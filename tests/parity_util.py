@@ -168,12 +168,16 @@ def compare_step(pb, st_o, st_g, dg_o, dg_g, f_o, f_g, report=None, excuse=None,
         tol_c = 2e-5 * sq * steps
         tol_w = 2e-5 * steps
     else:
-        tol_x = 1e-12 * L + 1e-9 * flown
-        tol_c = 1e-9 * sq * steps
         # a projected batch of a few particles solves a Gram system whose
         # condition number (up to 1e10 by its pivot test) multiplies the
-        # rounding of its inputs
-        tol_w = (1e-6 if pb.spawn_projection == 1 else 1e-9) * steps
+        # rounding of its inputs; the cell its particles fly to takes their
+        # weights into the mass, momentum and energy of its conservation
+        # correction, which passes the difference on to the weight and the
+        # velocity of every particle it reassigns
+        rel = 1e-6 if pb.spawn_projection == 1 else 1e-9
+        tol_x = 1e-12 * L + rel * flown
+        tol_c = rel * sq * steps
+        tol_w = rel * steps
     ties = tie_cells(dg_o)
     if excuse is not None:
         ties = ties | excuse
