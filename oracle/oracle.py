@@ -16,7 +16,7 @@ from . import build as _build
 NMOM = 13
 NCS = 4 * NMOM + 2
 NF = 18
-NDIAG = 32
+NDIAG = 33
 
 # per-cell record of the last step; "flags" is a bit set: 1 the cell's
 # moments were invalid (no relaxation), 2 the mass correction failed, 4 the
@@ -25,11 +25,13 @@ NDIAG = 32
 DIAG = dict(n_in=0, n4=1, n_sel=2, n_usp=3, n_del=4, n7=5, n_out=6, n2=7, s_sel=8, p_sel=9,
             flags=10, chol_fb=11, M0=12, P0x=13, P0y=14, P0z=15, E0=16, M1=17, P1x=18, P1y=19,
             P1z=20, E1=21, clamp=22, marg_sel=23, marg_round=24, marg_cnt=25, Wr=26, s2=27,
-            marg_cnt2=28, n_inj=29, n_gone=30, marg_face=31)
+            marg_cnt2=28, n_inj=29, n_gone=30, marg_face=31, marg_cons=32)
 # marg_face: the smallest distance (m) of a landing point of the step's
 # flights to a face this cell shares with another (interior or periodic),
 # kept in both cells of that face; the rounding of a flight that ends there
-# decides which of the two receives the particle
+# decides which of the two receives the particle.  marg_cons: the smallest
+# relative gap between a value the conservation correction tests (W_r, the
+# mean shift, s^2, the whole-cell conditions) and its bound
 
 
 class Config(C.Structure):

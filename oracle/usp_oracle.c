@@ -162,8 +162,25 @@ enum {
     D_NIN = 0, D_N4, D_NSEL, D_NUSP, D_NDEL, D_N7, D_NOUT, D_N2, D_SSEL, D_PSEL, D_FLAGS,
     D_CHOLFB, D_M0, D_P0X, D_P0Y, D_P0Z, D_E0, D_M1, D_P1X, D_P1Y, D_P1Z, D_E1, D_CLAMP,
     D_MARG_SEL, D_MARG_ROUND, D_MARG_CNT, D_WR, D_S2, D_MARG_CNT2, D_NINJ, D_NGONE,
-    D_MARG_FACE
+    D_MARG_FACE, D_MARG_CONS
 };
+
+/* Test diagnostics of the conservation correction's branch tests: keeps in
+ * *m the smallest relative gap between a tested value and its bound (a
+ * value that rounding alone could move across it takes either branch). */
+static void note_gap(double* m, double x, double bound)
+{
+    double s = fmax(fabs(x), fabs(bound));
+    double r = s > 0.0 ? fabs(x - bound) / s : 0.0;
+    if (r < *m) *m = r;
+}
+
+/* the same for a sign test of x = the sum of terms of total size `size` */
+static void note_sign(double* m, double x, double size)
+{
+    double r = size > 0.0 ? fabs(x) / size : 0.0;
+    if (r < *m) *m = r;
+}
 enum { F_SKIP = 1, F_FAILMASS = 2, F_FAILENERGY = 4, F_NOUSP = 8, F_WHOLE = 16 };
 
 struct uspo {
@@ -938,7 +955,7 @@ static void use_averaged_sh(const uspo* o, const double* avg_raw, cellf* f)
  * energy of the survivors and the step-7 particles. */
 static int whole_cell(const uspo* o, plist* L, const selinfo* si, int nl, plist* L7, int nusp,
                       double M0, const double P0[3], double E0, double Mr, const double Pr[3],
-                      double Er)
+                      double Er, double* gap)
 {
     const uspo_config* g = &o->g;
     double Wr = (M0 - Mr) / nusp;
@@ -960,6 +977,14 @@ static int whole_cell(const uspo* o, plist* L, const selinfo* si, int nl, plist*
     }
     double K = Er + 0.5 * Wr * sq - 0.5 * M * u2;
     double s2 = (E0 - 0.5 * M0 * a2) / K;
+    note_sign(gap, M0 - Mr, fabs(M0) + fabs(Mr));
+    note_sign(gap, M, fabs(Mr) + fabs(Wr * nusp));
+    note_sign(gap, K, fabs(Er) + fabs(0.5 * Wr * sq) + fabs(0.5 * M * u2));
+    if (K > 0.0 && M > 0.0) {
+        note_gap(gap, du2, 9.0 * 2.0 * K / M);
+        note_gap(gap, s2, 0.25);
+        note_gap(gap, s2, 4.0);
+    }
     ok = ok && M > 0.0 && K > 0.0 && du2 <= 9.0 * 2.0 * K / M && s2 >= 0.25 && s2 <= 4.0;
     if (!ok) return 0;
     double s = sqrt(s2);
@@ -981,7 +1006,7 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
     const uspo_config* g = &o->g;
     int n0 = L->n;
     dg[D_NIN] = n0;
-    dg[D_MARG_SEL] = dg[D_MARG_ROUND] = dg[D_MARG_CNT] = INFINITY;
+    dg[D_MARG_SEL] = dg[D_MARG_ROUND] = dg[D_MARG_CNT] = dg[D_MARG_CONS] = INFINITY;
     double mom[USPO_MOM];
     moments(L->p, n0, mom);
     double M0, P0[3], E0;
@@ -1115,6 +1140,8 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
             } else {
                 double Wr = (M0 - Mr) / nusp;
                 dg[D_WR] = Wr;
+                note_gap(&dg[D_MARG_CONS], Wr, 0.5);
+                note_gap(&dg[D_MARG_CONS], Wr, 2.0);
                 if (!(Wr >= 0.5 && Wr <= 2.0)) {
                     flags |= F_FAILMASS;
                 } else {
@@ -1138,6 +1165,7 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
                     double s = 1.0;
                     int shift = 1;
                     if (nusp >= 2 && D > 0.0) {
+                        note_gap(&dg[D_MARG_CONS], da2, 9.0 * D / nusp);
                         if (!(da2 <= 9.0 * D / nusp)) {
                             /* the mean would move by more than 3 rms spreads */
                             shift = 0;
@@ -1145,6 +1173,8 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
                         } else {
                             double s2 = (E0 - Er - 0.5 * MR * a2) / (0.5 * Wr * D);
                             dg[D_S2] = s2;
+                            note_gap(&dg[D_MARG_CONS], s2, 1.0 / 9.0);
+                            note_gap(&dg[D_MARG_CONS], s2, 9.0);
                             if (s2 >= 1.0 / 9.0 && s2 <= 9.0) s = sqrt(s2);
                             else flags |= F_FAILENERGY;
                         }
@@ -1152,7 +1182,7 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
                         flags |= F_FAILENERGY;
                     }
                     int whole = (flags & F_FAILENERGY) &&
-                                whole_cell(o, L, si, nl, &L7, nusp, M0, P0, E0, Mr, Pr_, Er);
+                                whole_cell(o, L, si, nl, &L7, nusp, M0, P0, E0, Mr, Pr_, Er, &dg[D_MARG_CONS]);
                     if (whole)
                         flags = (flags & ~F_FAILENERGY) | F_WHOLE;
                     else
@@ -1166,7 +1196,7 @@ static void relax_cell(uspo* o, int d, plist* L, double* dg)
                             }
                 }
                 if ((flags & F_FAILMASS) &&
-                    whole_cell(o, L, si, nl, &L7, nusp, M0, P0, E0, Mr, Pr_, Er))
+                    whole_cell(o, L, si, nl, &L7, nusp, M0, P0, E0, Mr, Pr_, Er, &dg[D_MARG_CONS]))
                     flags = (flags & ~F_FAILMASS) | F_WHOLE;
             }
         }

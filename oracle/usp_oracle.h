@@ -86,7 +86,7 @@ typedef struct {
 /* derived field record (see uspo_get_fields) */
 #define USPO_NF 18
 /* per-cell diagnostics of the last step */
-#define USPO_NDIAG 32
+#define USPO_NDIAG 33
 
 typedef struct uspo uspo;
 
