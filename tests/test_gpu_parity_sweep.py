@@ -179,6 +179,20 @@ def test_random_workload_parity(ctx, k):
     print(label, "two steps", _run(ctx, pb, first, st, 2), flush=True)
 
 
+# draws beyond the sweep's range whose comparisons each fixed a reading of
+# the bars: the propagated velocity term of the multi-step position bar
+# (1781), a shared-face tie (2636), the arrivals' weight term of the
+# multi-step moment bar (2647, 4353), the projection term of the FP64
+# velocity bar (4716, 5448) and a conservation-branch tie (6083)
+READING_DRAWS = [1781, 2636, 2647, 4353, 4716, 5448, 6083]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("k", READING_DRAWS)
+def test_reading_draws_parity(ctx, k):
+    test_random_workload_parity(ctx, k)
+
+
 NBATCH, PER_BATCH = 12, 6
 
 
