@@ -113,11 +113,12 @@ def _oracle_state(pb, warm):
 
 
 def test_sweep_draws_are_valid_oracle_states():
-    """CPU: every draw of the sweep is one the oracle takes through its
-    warm-up and the compared steps without an error, and the draws cover
-    every problem kind, both precisions and every launch shape"""
+    """CPU: every draw of the sweep (and every regression draw) is one the
+    oracle takes through its warm-up and the compared steps without an
+    error, and the draws cover every problem kind, both precisions and every
+    launch shape"""
     kinds, precs, shapes = set(), set(), set()
-    for k in range(NCASE):
+    for k in list(range(NCASE)) + READING_DRAWS:
         label, pb, first, warm = draw_case(k)
         assert _oracle_state(pb, warm + 2) is not None, label
         kinds.add(label.split("-")[1])
